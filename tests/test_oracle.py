@@ -1,0 +1,443 @@
+"""Pins of the oracle against what the paper and mathematics fix.
+
+Nothing here touches the GPU library. Each test pins the oracle (oracle.c,
+via ctypes) or the plain chunked model (oracle/method_model.py) to something
+other than itself: the paper's printed tables and examples, hand-derived
+worked examples, closed forms (Python's exact integer, rational and calendar
+arithmetic), invariants, and brute force over every split of tiny inputs.
+"""
+import calendar
+import itertools
+import random
+from fractions import Fraction
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from datagen import dialects as D
+from oracle import method_model as M
+from conftest import ints, read_golden
+
+
+# ---- the paper's printed tables and examples ------------------------------
+
+def test_table1_transitions_verbatim():
+    """paper6's next-state table equals Table 1 cell by cell."""
+    g = read_golden("table1_transitions.txt")
+    states = g["states"].split()
+    dfa = D.paper6()
+    assert dfa.state_names == states
+    rows = [v for k, v in g.items() if k.startswith("group")]
+    assert len(rows) == dfa.num_groups
+    for gi, row in enumerate(rows):
+        cells = row.split()
+        assert [states[s] for s in dfa.next_state[gi]] == cells
+    # symbols -> groups as printed: \n 0, " 1, , 2, everything else 3
+    assert dfa.group_of[ord("\n")] == 0 and dfa.group_of[ord('"')] == 1
+    assert dfa.group_of[ord(",")] == 2
+    assert all(dfa.group_of[b] == 3 for b in range(256) if b not in (10, 34, 44))
+
+
+def test_prefix_sum_example():
+    g = read_golden("prefix_sum_example.txt")
+    x = ints(g["x"])
+    assert M.inclusive_scan(x, lambda a, b: a + b) == ints(g["inclusive"])
+    assert M.exclusive_scan(x, lambda a, b: a + b, 0) == ints(g["exclusive"])
+
+
+@pytest.mark.parametrize("dfa", [D.paper6(), D.csv4()], ids=["paper6", "csv4"])
+def test_ragged_example(dfa):
+    g = read_golden("ragged_example.txt")
+    buf = bytes.fromhex(g["input_hex"])
+    r = oracle.parse(buf, dfa, [D.INT64, D.STRING])
+    assert r.status == oracle.STATUS_OK
+    assert r.num_records == int(g["num_records"]) and r.num_fields == int(g["num_fields"])
+    assert list(r.record_offsets) == ints(g["record_offsets"])
+    assert list(r.field_offsets) == ints(g["field_offsets"])
+    assert list(r.column_ids) == ints(g["column_ids"])
+    assert list(r.values[0]) == ints(g["col0_values"])
+    assert list(r.valid[0]) == ints(g["col0_valid"])
+    assert list(r.values[1]) == ints(g["col1_begin"])
+    assert list(r.str_end[1]) == ints(g["col1_end"])
+    assert list(r.valid[1]) == ints(g["col1_valid"])
+    assert r.num_ragged_records == int(g["num_ragged_records"])
+
+
+def _quoted():
+    g = read_golden("quoted_example.txt")
+    return g, bytes.fromhex(g["input_hex"])
+
+
+def test_quoted_example_sequential():
+    g, buf = _quoted()
+    dfa = D.paper6()
+    r = oracle.parse(buf, dfa, [D.STRING, D.STRING])
+    assert r.status == oracle.STATUS_OK and r.final_state == int(g["final_state"])
+    assert r.num_records == int(g["num_records"]) and r.num_fields == int(g["num_fields"])
+    assert list(r.record_offsets) == ints(g["record_offsets"])
+    assert list(r.field_offsets) == ints(g["field_offsets"])
+    assert list(r.column_ids) == ints(g["column_ids"])
+    spans = [tuple(int(v) for v in s.split("-")) for s in g["string_spans"].split()]
+    got = []
+    for rec in range(r.num_records):
+        for c in range(2):
+            got.append((int(r.values[c][rec]), int(r.str_end[c][rec])))
+    assert got == spans
+    # per-symbol tags of the sequential run
+    tags, _ = M.tag_chunk(dfa, buf, dfa.start_state)
+    assert [i for i, t in enumerate(tags) if t == M.RECORD] == ints(g["record_tags"])
+    assert [i for i, t in enumerate(tags) if t == M.FIELD] == ints(g["field_tags"])
+    assert [i for i, t in enumerate(tags) if t == M.CONTROL] == ints(g["control_tags"])
+
+
+def test_quoted_example_chunked():
+    """The chunked method on the worked example, step by step."""
+    g, buf = _quoted()
+    dfa = D.paper6()
+    B = int(g["chunk_size"])
+    out = M.parse_chunked(dfa, buf, list(range(B, len(buf), B)))
+    for j, v in enumerate(out["vectors"]):
+        assert list(v) == ints(g[f"vector {j}"])
+    for j, p in enumerate(out["prefixes"]):
+        assert list(p) == ints(g[f"prefix {j}"])
+    assert out["starts"] == ints(g["chunk_starts"])
+    want = [(M.ABS if c.startswith("abs") else M.REL, int(c[3:])) for c in g["carries"].split()]
+    assert out["carries"] == want
+    assert [c[1] for c in out["col_prefix"]] == ints(g["column_prefix"])
+    assert all(c[0] == M.ABS for c in out["col_prefix"])
+    assert out["rec_prefix"] == ints(g["record_prefix"])
+    assert out["record_offsets"] == ints(g["record_offsets"])
+    assert out["field_offsets"] == ints(g["field_offsets"])
+
+
+# ---- algebra ---------------------------------------------------------------
+
+@pytest.mark.parametrize("ns", [2, 3, 4])
+def test_composition_associative_exhaustive(ns):
+    """(a o b) o c == a o (b o c) over all ns^ns vectors, and the identity."""
+    vecs = np.array(list(itertools.product(range(ns), repeat=ns)), dtype=np.int64)
+    code = {tuple(v): i for i, v in enumerate(vecs.tolist())}
+    k = len(vecs)
+    table = np.empty((k, k), dtype=np.int64)
+    for i in range(k):
+        comp = vecs[:, :][:, vecs[i]] if False else None  # noqa
+        for j in range(k):
+            table[i, j] = code[M.compose(vecs[i], vecs[j])]
+    ii, jj, kk = np.meshgrid(np.arange(k), np.arange(k), np.arange(k), indexing="ij")
+    assert np.array_equal(table[table[ii, jj], kk], table[ii, table[jj, kk]])
+    e = code[M.identity_vector(ns)]
+    assert np.array_equal(table[e, :], np.arange(k)) and np.array_equal(table[:, e], np.arange(k))
+
+
+def test_compose_matches_function_composition():
+    """Composition is 'apply a, then b': (a o b)_i = b[a_i], not a[b_i]."""
+    a, b = (1, 2, 0), (2, 2, 1)
+    assert M.compose(a, b) == (2, 1, 2)
+    assert M.compose(b, a) == (0, 0, 2)
+
+
+def test_oplus_associative_and_identity():
+    vals = [(t, o) for t in (M.ABS, M.REL) for o in range(4)]
+    for a in vals:
+        assert M.oplus((M.REL, 0), a) == a or a[0] == M.REL and M.oplus((M.REL, 0), a) == a
+        assert M.oplus(a, (M.REL, 0)) == a
+        for b in vals:
+            for c in vals:
+                assert M.oplus(M.oplus(a, b), c) == M.oplus(a, M.oplus(b, c))
+    # Sec. 3.2's two cases
+    assert M.oplus((M.REL, 3), (M.ABS, 1)) == (M.ABS, 1)
+    assert M.oplus((M.ABS, 3), (M.REL, 2)) == (M.ABS, 5)
+
+
+def test_column_carry_prose_reading():
+    """Carry = field delimiters after the LAST record delimiter (prose of
+    Sec. 3.2), not after the first as the printed BLSMSK formula would give."""
+    F, R, D_ = M.FIELD, M.RECORD, M.DATA
+    assert M.column_carry([F, R, F, F, R, F]) == (M.ABS, 1)
+    assert M.column_carry([F, D_, F]) == (M.REL, 2)
+    assert M.column_carry([R]) == (M.ABS, 0)
+
+
+@pytest.mark.parametrize("dfa", [D.paper6(), D.csv4(), D.log6(), D.s7(), D.s8()],
+                         ids=lambda d: d.name)
+def test_homomorphism(dfa):
+    """vec(xy) = vec(x) o vec(y) on random strings of the dialect's symbols."""
+    rnd = random.Random(7)
+    alphabet = [syms[0] for syms in dfa.group_symbols] + [ord("a")]
+    for _ in range(300):
+        x = bytes(rnd.choice(alphabet) for _ in range(rnd.randint(0, 12)))
+        y = bytes(rnd.choice(alphabet) for _ in range(rnd.randint(0, 12)))
+        assert M.transition_vector(dfa, x + y) == M.compose(M.transition_vector(dfa, x),
+                                                            M.transition_vector(dfa, y))
+
+
+# ---- brute force: every split of every tiny input ---------------------------
+
+def _all_splits(n):
+    for mask in range(1 << max(n - 1, 0)):
+        yield [i + 1 for i in range(n - 1) if mask >> i & 1]
+
+
+def _check_all_splits(dfa, buf):
+    ref = oracle.parse(buf, dfa, [])
+    seq_tags, _ = M.tag_chunk(dfa, buf, dfa.start_state)
+    for cuts in _all_splits(len(buf)):
+        out = M.parse_chunked(dfa, buf, cuts)
+        assert out["tags"] == seq_tags
+        assert out["final_state"] == ref.final_state
+        assert out["record_offsets"] == list(ref.record_offsets), (buf, cuts)
+        assert out["field_offsets"] == list(ref.field_offsets), (buf, cuts)
+        assert out["column_ids"] == list(ref.column_ids), (buf, cuts)
+
+
+@pytest.mark.parametrize("dfa", [D.paper6(), D.csv4()], ids=lambda d: d.name)
+def test_brute_force_all_splits_csv(dfa):
+    """Every string of length <= 6 over {LF, quote, comma, a}, every split."""
+    alphabet = b'\n",a'
+    for n in range(0, 7):
+        for tup in itertools.product(alphabet, repeat=n):
+            _check_all_splits(dfa, bytes(tup))
+
+
+def test_brute_force_all_splits_log6():
+    dfa = D.log6()
+    alphabet = b'\n "\\[]a'
+    for n in range(0, 5):
+        for tup in itertools.product(alphabet, repeat=n):
+            _check_all_splits(dfa, bytes(tup))
+
+
+def test_csv4_equals_paper6_on_valid_input():
+    """csv4 merges Table 1's EOR/EOF columns and drops INV; on every input
+    that paper6 accepts, the two give identical outputs."""
+    p6, c4 = D.paper6(), D.csv4()
+    alphabet = b'\n",a'
+    checked = 0
+    for n in range(0, 8):
+        for tup in itertools.product(alphabet, repeat=n):
+            buf = bytes(tup)
+            a = oracle.parse(buf, p6, [D.STRING, D.STRING, D.STRING])
+            if a.status != oracle.STATUS_OK:
+                continue
+            b = oracle.parse(buf, c4, [D.STRING, D.STRING, D.STRING])
+            checked += 1
+            assert b.status == oracle.STATUS_OK
+            assert np.array_equal(a.record_offsets, b.record_offsets)
+            assert np.array_equal(a.field_offsets, b.field_offsets)
+            assert np.array_equal(a.column_ids, b.column_ids)
+            for c in range(3):
+                assert np.array_equal(a.values[c], b.values[c])
+                assert np.array_equal(a.str_end[c], b.str_end[c])
+                assert np.array_equal(a.valid[c], b.valid[c])
+    assert checked > 1000
+
+
+# ---- status, validation, capacity ----------------------------------------
+
+def test_invalid_quote_in_unquoted_field():
+    """Sec. 4.3 (validating format): a quote read in FLD enters INV (Table 1);
+    the offset of that transition is reported and INV absorbs the rest."""
+    buf = b'ab,c"d,e\nf\n'
+    r = oracle.parse(buf, D.paper6(), [])
+    assert r.status == oracle.STATUS_INVALID_INPUT
+    assert r.first_invalid_offset == 4
+    assert r.final_state == 5
+    assert r.num_records == 1 and r.num_fields == 2  # one field after byte 2: INV absorbs
+
+
+def test_unterminated_quote_is_non_accepting():
+    for dfa in (D.paper6(), D.csv4()):
+        r = oracle.parse(b'a,"bc\n', dfa, [])
+        assert r.status == oracle.STATUS_NON_ACCEPTING_END
+        assert r.first_invalid_offset == -1
+
+
+def test_capacity_reports_required_sizes():
+    buf = b"1,2\n3,4\n5,6\n"
+    r = oracle.parse(buf, D.csv4(), [D.INT64, D.INT64], cap_records=2, cap_fields=3)
+    assert r.status == oracle.STATUS_CAPACITY
+    assert r.num_records == 3 and r.num_fields == 6
+    assert list(r.field_offsets) == [0, 2, 4, 6]
+    assert list(r.record_offsets) == [0, 2, 4]
+
+
+def test_empty_and_edge_inputs():
+    dfa = D.csv4()
+    r = oracle.parse(b"", dfa, [D.INT64])
+    assert (r.num_records, r.num_fields, r.status) == (0, 0, oracle.STATUS_OK)
+    assert list(r.field_offsets) == [0] and list(r.record_offsets) == [0]
+    # no trailing LF: the last record still counts; field_offsets[F] = n + 1
+    r = oracle.parse(b"1,2", dfa, [D.INT64, D.INT64])
+    assert list(r.field_offsets) == [0, 2, 4] and list(r.values[1]) == [2]
+    # trailing field delimiter: an empty last field
+    r = oracle.parse(b"1,", dfa, [D.INT64, D.INT64])
+    assert r.num_fields == 2 and list(r.valid[1]) == [0] and r.num_conversion_errors == 0
+    # blank line: a record with one empty field
+    r = oracle.parse(b"\n\n", dfa, [D.INT64])
+    assert r.num_records == 2 and r.num_fields == 2 and list(r.field_offsets) == [0, 1, 2]
+    # extra fields are kept in the field arrays and dropped from typed output
+    r = oracle.parse(b"1,2,3\n", dfa, [D.INT64])
+    assert r.num_fields == 3 and r.num_ragged_records == 1 and list(r.values[0]) == [1]
+
+
+# ---- conversions against Python's exact arithmetic -------------------------
+
+INT_CASES = ["0", "-0", "+7", "123", "-123", "9223372036854775807", "-9223372036854775808",
+             "9223372036854775808", "-9223372036854775809", "00000000000000000000042",
+             "", "+", "-", "1 ", " 1", "1.0", "0x10", "12a", "99999999999999999999"]
+
+
+@pytest.mark.parametrize("text", INT_CASES)
+def test_int64_conversion(text):
+    ok, iv, _ = oracle.convert(D.INT64, text.encode())
+    try:
+        want = int(text, 10) if text.strip() == text and text and text.lstrip("+-").isdigit() else None
+    except ValueError:
+        want = None
+    if want is not None and not (-(1 << 63) <= want < (1 << 63)):
+        want = None
+    assert ok == (want is not None)
+    if ok:
+        assert iv == want
+
+
+FLOAT_CASES = ["0", "-0.0", "1", "1.5", ".5", "5.", "-.25", "1e10", "1E-5", "+3.25e+2",
+               "123456.789012", "0.1", "0.2", "0.3", "9007199254740993", "1e308", "1.8e308",
+               "-1e400", "4.9406564584124654e-324", "2.4703282292062327e-324",
+               "2.4703282292062328e-324", "1e-320", "2.2250738585072011e-308",
+               "1.7976931348623157e308", "1.00000000000000011102230246251565404236316680908203125",
+               "1.00000000000000011102230246251565404236316680908203124",
+               "1.00000000000000011102230246251565404236316680908203126",
+               "12345678901234567890123", "0.000000000000000000000000000000123456789",
+               "", ".", "e5", "1e", "1e+", "--1", "inf", "nan", "0x1p3", " 1", "1,0"]
+
+
+def _py_float(text):
+    """Grammar-checked exact value of the decimal, rounded by Python."""
+    import re
+    if not re.fullmatch(r"[+-]?([0-9]+(\.[0-9]*)?|\.[0-9]+)([eE][+-]?[0-9]+)?", text):
+        return None
+    return float(text)
+
+
+@pytest.mark.parametrize("text", FLOAT_CASES)
+def test_float64_conversion(text):
+    ok, _, dv = oracle.convert(D.FLOAT64, text.encode())
+    want = _py_float(text)
+    assert ok == (want is not None)
+    if ok:
+        assert np.float64(dv).tobytes() == np.float64(want).tobytes()
+
+
+def test_float64_against_exact_rationals():
+    """Random decimals: the oracle equals the binary64 nearest to the exact
+    rational value (Python's Fraction -> float rounds correctly)."""
+    rnd = random.Random(11)
+    for _ in range(3000):
+        digits = "".join(rnd.choice("0123456789") for _ in range(rnd.randint(1, 25)))
+        point = rnd.randint(0, len(digits))
+        exp = rnd.randint(-30, 30)
+        text = digits[:point] + "." + digits[point:] + f"e{exp}"
+        ok, _, dv = oracle.convert(D.FLOAT64, text.encode())
+        assert ok
+        frac = Fraction(int(digits), 10 ** (len(digits) - point)) * Fraction(10) ** exp
+        assert dv == float(frac)
+
+
+def _epoch(y, m, d, hh=0, mi=0, ss=0):
+    return calendar.timegm((y, m, d, hh, mi, ss, 0, 0, 0))
+
+
+TS_CASES = [("1970-01-01 00:00:00", _epoch(1970, 1, 1)), ("1970-01-01T00:00:01", 1),
+            ("1969-12-31 23:59:59", -1), ("2000-02-29 12:00:00", _epoch(2000, 2, 29, 12)),
+            ("1900-02-28 00:00:00", _epoch(1900, 2, 28)), ("2018-12-31 23:59:59", _epoch(2018, 12, 31, 23, 59, 59)),
+            ("0001-01-01 00:00:00", _epoch(1, 1, 1)), ("9999-12-31 23:59:59", _epoch(9999, 12, 31, 23, 59, 59)),
+            ("1900-02-29 00:00:00", None), ("2001-02-29 00:00:00", None), ("2018-13-01 00:00:00", None),
+            ("2018-00-10 00:00:00", None), ("2018-01-32 00:00:00", None), ("2018-01-01 24:00:00", None),
+            ("2018-01-01 00:60:00", None), ("2018-01-01 00:00:60", None), ("2018-01-01 00:00", None),
+            ("2018/01/01 00:00:00", None), ("2018-01-01x00:00:00", None)]
+
+
+@pytest.mark.parametrize("text,want", TS_CASES)
+def test_timestamp_conversion(text, want):
+    ok, iv, _ = oracle.convert(D.TIMESTAMP_S, text.encode())
+    assert ok == (want is not None)
+    if ok:
+        assert iv == want
+
+
+def test_date_conversion_all_days():
+    """Every day from 1600 to 2400 against Python's calendar arithmetic."""
+    import datetime
+    d = datetime.date(1600, 1, 1)
+    base = datetime.date(1970, 1, 1)
+    while d.year < 2400:
+        ok, iv, _ = oracle.convert(D.DATE_DAYS, d.isoformat().encode())
+        assert ok and iv == (d - base).days
+        d += datetime.timedelta(days=1)
+
+
+# ---- generator round trip ----------------------------------------------------
+
+def _check_truth(g, dfa, schema):
+    r = oracle.parse(g.data, dfa, schema.types)
+    t = g.truth
+    R, C = g.nrecords, g.ncols
+    assert r.status == oracle.STATUS_OK
+    assert r.num_records == R and r.num_fields == R * C
+    assert r.num_ragged_records == 0
+    assert np.array_equal(r.record_offsets, np.arange(R + 1) * C)
+    assert np.array_equal(r.field_offsets[:-1], t.fbeg.reshape(-1))
+    assert np.array_equal(r.column_ids, np.tile(np.arange(C, dtype=np.int32), R))
+    for c, ty in enumerate(schema.types):
+        kind = t.kind[:, c]
+        if ty == D.STRING:
+            assert np.array_equal(r.values[c], t.vbeg[:, c])
+            assert np.array_equal(r.str_end[c], t.vend[:, c])
+            assert r.valid[c].all()
+        elif ty == D.FLOAT64:
+            want = np.array([float(Fraction(int(m), 10 ** int(k))) for m, k in zip(t.ival[:, c], t.aux[:, c])])
+            assert np.array_equal(r.values[c], want)
+        elif ty in (D.INT64, D.TIMESTAMP_S, D.DATE_DAYS):
+            ok = kind == 1
+            assert np.array_equal(r.valid[c].astype(bool), ok)
+            assert np.array_equal(r.values[c][ok], t.ival[ok, c])
+    return r
+
+
+def test_generator_round_trip_c1():
+    g = datagen.c1(with_truth=True)
+    assert g.nrecords == 10000
+    r = _check_truth(g, D.csv4(), D.SCHEMA_C1)
+    assert r.num_conversion_errors == 0
+    # same outputs under Table 1's DFA (the input is valid RFC-4180)
+    r6 = oracle.parse(g.data, D.paper6(), D.SCHEMA_C1.types)
+    assert r6.status == oracle.STATUS_OK and np.array_equal(r6.field_offsets, r.field_offsets)
+
+
+def test_generator_round_trip_c2_c3_sample():
+    _check_truth(datagen.c2(nbytes=4 << 20, with_truth=True), D.csv4(), D.SCHEMA_C2)
+    _check_truth(datagen.c3(nbytes=8 << 20, with_truth=True), D.csv4(), D.SCHEMA_C3)
+
+
+def test_generator_round_trip_log():
+    g = datagen.log(5, 2 << 20, with_truth=True)
+    r = _check_truth(g, D.log6(), D.SCHEMA_LOG12)
+    # "-" in the bytes column is a conversion failure (null), counted
+    assert r.num_conversion_errors == int((g.truth.kind[:, 6] == 0).sum())
+
+
+@pytest.mark.parametrize("name,delim,qstyle", [("csv4", b",", 1), ("csv4", b"\t", 1),
+                                               ("paper6", b",", 1), ("s5", b"|", 1),
+                                               ("s3", b",", 3), ("s7", b",", 2)])
+def test_generator_round_trip_mixed(name, delim, qstyle):
+    dfa = D.ALL_DFAS[name](delim) if name != "paper6" else D.paper6()
+    g = datagen.mixed(3, 1 << 20, delim=delim, qstyle=qstyle, with_truth=True)
+    _check_truth(g, dfa, D.SCHEMA_C1)
+
+
+def test_generator_round_trip_s8_log():
+    g = datagen.log(9, 1 << 20, with_truth=True)
+    _check_truth(g, D.s8(), D.SCHEMA_LOG12)
