@@ -1,0 +1,157 @@
+/*
+ * parparaw.h -- C ABI of the MI355X (gfx950) parallel parser for
+ * delimiter-separated text.
+ *
+ * The method is that of "ParPaRaw: Massively Parallel Parsing of
+ * Delimiter-Separated Raw Data" (Stehle & Jacobsen, PVLDB 13(5), 2020):
+ *  - Sec. 3.1: every chunk of the input is simulated from every DFA state,
+ *    giving a state-transition vector; an exclusive scan of the vectors under
+ *    composition gives every chunk its start state; a second pass from that
+ *    state tags record delimiters, field delimiters and control symbols;
+ *  - Sec. 3.2: record counts are prefix-summed into record offsets, column
+ *    carries are scanned with the abs/rel operator into column offsets;
+ *  - Sec. 3.3: fields are grouped by column and converted to typed columns;
+ *  - Sec. 4.3: invalid transitions and non-accepting end states are
+ *    reported, empty fields take the column default.
+ *
+ * All pointers named d_* are device pointers (HBM of the GPU that is
+ * current when the call is made); everything else is host memory. Nothing
+ * here allocates device memory: the caller owns inputs, outputs and
+ * workspace. Calls are asynchronous on the given HIP stream and do no host
+ * synchronisation, so they may be captured into a HIP graph. Errors in the
+ * arguments are returned synchronously before any launch; outcomes that
+ * depend on the data (invalid input, capacity) are written to the device
+ * result record and are not errors.
+ *
+ * No function prints, aborts or throws. Functions are thread-safe as long as
+ * concurrent calls use distinct workspaces and outputs.
+ */
+#ifndef PARPARAW_H
+#define PARPARAW_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pp_status_t;
+#define PP_OK 0
+#define PP_ERR_ARG (-1)         /* null pointer, negative size, bad option */
+#define PP_ERR_DFA (-2)         /* DFA out of range or invalid state not absorbing */
+#define PP_ERR_SCHEMA (-3)      /* too many columns or unknown type */
+#define PP_ERR_WORKSPACE (-4)   /* workspace smaller than pp_workspace_size() */
+#define PP_ERR_HIP (-5)         /* a HIP launch failed */
+#define PP_ERR_UNSUPPORTED (-6) /* a combination this build does not support */
+
+/* Symbol tags (Sec. 3.1: record delimiter, field delimiter, control symbol,
+ * or part of a field's value). */
+#define PP_TAG_DATA 0
+#define PP_TAG_CONTROL 1
+#define PP_TAG_FIELD 2
+#define PP_TAG_RECORD 3
+
+/* Column types (Sec. 3.3 names integer, float and temporal conversions). */
+#define PP_INT64 0       /* [+-]?[0-9]+ fitting int64 */
+#define PP_FLOAT64 1     /* decimal, correctly rounded to nearest, ties to even */
+#define PP_TIMESTAMP_S 2 /* YYYY-MM-DD hh:mm:ss or YYYY-MM-DDThh:mm:ss -> int64 s since 1970 UTC */
+#define PP_DATE_DAYS 3   /* YYYY-MM-DD -> int64 days since 1970-01-01 */
+#define PP_STRING 4      /* (begin, end) int64 byte span, enclosing control symbols stripped */
+#define PP_SKIP 5        /* no typed output */
+
+#define PP_MAX_STATES 8
+#define PP_MAX_GROUPS 16
+#define PP_MAX_COLUMNS 64
+
+/* A DFA with a Mealy tag table. Tables are indexed [group][state], with
+ * symbol groups as rows and states as columns (Table 1, Sec. 4.5).
+ * Copied during the call. */
+typedef struct {
+    int32_t num_states;    /* 1..PP_MAX_STATES */
+    int32_t num_groups;    /* 1..PP_MAX_GROUPS */
+    int32_t start_state;   /* state before the first byte */
+    int32_t invalid_state; /* -1: none; else it must be absorbing (all next = itself) */
+    uint32_t accept_mask;  /* bit s set: ending in state s is accepted */
+    uint8_t group_of[256]; /* symbol -> group */
+    uint8_t next[16][16];  /* [group][state] -> next state */
+    uint8_t tag[16][16];   /* [group][state] -> PP_TAG_* */
+} pp_dfa_t;
+
+/* Result record, written by the device (asynchronously). */
+#define PP_RESULT_OK 0
+#define PP_RESULT_INVALID_INPUT 1     /* a transition entered invalid_state */
+#define PP_RESULT_NON_ACCEPTING_END 2 /* final state not in accept_mask */
+#define PP_RESULT_CAPACITY 3          /* R > cap_records or F > cap_fields */
+typedef struct {
+    int64_t status;               /* CAPACITY, else INVALID_INPUT, else NON_ACCEPTING_END, else OK */
+    int64_t num_records;          /* R (required size, even beyond capacity) */
+    int64_t num_fields;           /* F */
+    int64_t first_invalid_offset; /* byte of the transition into invalid_state, or -1 */
+    int64_t final_state;
+    int64_t num_conversion_errors; /* non-empty numeric fields that failed to convert */
+    int64_t num_ragged_records;    /* records whose field count differs from ncols */
+} pp_result_t;
+
+/*
+ * Outputs, all caller-allocated device memory (host struct of device pointers).
+ *  d_record_offsets[cap_records + 1]: record r's first field index; [R] = F.
+ *  d_field_offsets[cap_fields + 1]: field f's first byte; [F] = one past the
+ *      last field's terminating delimiter (n + 1 when the input does not end
+ *      in a record delimiter, since end of input then closes the last record).
+ *  d_column_ids[cap_fields]: field f's position within its record.
+ *  Per column c < ncols (by type):
+ *      d_values[c][cap_records]: int64 (INT64, TIMESTAMP_S, DATE_DAYS, and
+ *          the span begin for STRING) or double (FLOAT64);
+ *      d_valid[c][cap_records]: 1 if present and converted, else 0 (value 0);
+ *      d_str_end[c][cap_records]: span end, STRING columns only.
+ *  Entries beyond a capacity are never written. d_values/d_valid/d_str_end
+ *  are host arrays of ncols device pointers (NULL entries for SKIP).
+ */
+typedef struct {
+    int64_t cap_records;
+    int64_t cap_fields;
+    int64_t* d_record_offsets;
+    int64_t* d_field_offsets;
+    int32_t* d_column_ids;
+    void* const* d_values;
+    uint8_t* const* d_valid;
+    int64_t* const* d_str_end;
+    pp_result_t* d_result;
+} pp_outputs_t;
+
+typedef struct {
+    int32_t ncols;        /* 0..PP_MAX_COLUMNS */
+    const int32_t* types; /* host array of ncols PP_* types */
+} pp_schema_t;
+
+/* Launch shape. bytes_per_thread is the chunk size of Sec. 3.1. */
+typedef struct {
+    int32_t bytes_per_thread; /* 0 = default; supported: 16, 32 */
+    int32_t block_threads;    /* 0 = default; supported: 256 */
+} pp_options_t;
+
+/* Device scratch that pp_parse needs for an input of n bytes (tile counter
+ * and the per-tile lookback words of the single-pass scans). */
+size_t pp_workspace_size(int64_t n, const pp_options_t* opts);
+
+/*
+ * Parse d_in[0..n) under dfa into the outputs (Sec. 3.1-3.3, 4.3).
+ * d_in: device bytes, read only, any alignment (16-byte alignment is faster).
+ * d_ws: device workspace of at least pp_workspace_size(n, opts) bytes,
+ *       owned by the caller and not shared with a concurrent call.
+ * opts: NULL for defaults. stream: a hipStream_t, or NULL for the null stream.
+ * Returns PP_OK once the work is enqueued.
+ */
+pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
+                     const pp_schema_t* schema, const pp_outputs_t* out,
+                     void* d_ws, size_t ws_bytes, const pp_options_t* opts,
+                     void* stream);
+
+/* Static text for a pp_status_t. */
+const char* pp_status_str(pp_status_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

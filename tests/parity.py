@@ -1,0 +1,54 @@
+"""Element-by-element comparison of the GPU parse with the oracle."""
+import numpy as np
+
+import oracle
+import paper_1905_13415_amd as pp
+
+
+def gpu_parse(data, dfa, types, cap_records=None, cap_fields=None, opts=None, offset=0):
+    """Run the GPU parse of ``data`` (numpy uint8); returns (Outputs, result dict).
+    ``offset`` shifts the input inside a larger device buffer (unaligned start)."""
+    import torch
+    if cap_records is None or cap_fields is None:
+        r, f = oracle.count(data, dfa)
+        cap_records = r if cap_records is None else cap_records
+        cap_fields = f if cap_fields is None else cap_fields
+    host = torch.from_numpy(np.ascontiguousarray(data))
+    if offset:
+        buf = torch.zeros(len(data) + offset, dtype=torch.uint8, device="cuda")
+        buf[offset:] = host.cuda()
+        d_in = buf[offset:]
+    else:
+        d_in = host.cuda()
+    out = pp.parse(d_in, dfa, types, cap_records, cap_fields, opts=opts)
+    torch.cuda.synchronize()
+    return out, out.result_dict()
+
+
+def assert_same(data, dfa, types, opts=None, offset=0, cap_records=None, cap_fields=None):
+    """Bit-exact parity of every output and result field."""
+    ref = oracle.parse(data, dfa, types, cap_records=cap_records, cap_fields=cap_fields)
+    out, res = gpu_parse(data, dfa, types, cap_records=cap_records, cap_fields=cap_fields,
+                         opts=opts, offset=offset)
+    want = {"status": ref.status, "num_records": ref.num_records, "num_fields": ref.num_fields,
+            "first_invalid_offset": ref.first_invalid_offset, "final_state": ref.final_state,
+            "num_conversion_errors": ref.num_conversion_errors,
+            "num_ragged_records": ref.num_ragged_records}
+    assert res == want
+    R = min(ref.num_records, out.cap_records)
+    F = min(ref.num_fields, out.cap_fields)
+    np.testing.assert_array_equal(out.record_offsets[:R + 1].cpu().numpy(), ref.record_offsets[:R + 1])
+    np.testing.assert_array_equal(out.field_offsets[:F + 1].cpu().numpy(), ref.field_offsets[:F + 1])
+    np.testing.assert_array_equal(out.column_ids[:F].cpu().numpy(), ref.column_ids[:F])
+    for c, ty in enumerate(types):
+        if ty == pp.SKIP:
+            continue
+        gv = out.values[c][:R].cpu().numpy()
+        rv = ref.values[c][:R]
+        # floats compared bit for bit
+        np.testing.assert_array_equal(gv.view(np.int64), rv.view(np.int64), err_msg=f"column {c}")
+        np.testing.assert_array_equal(out.valid[c][:R].cpu().numpy(), ref.valid[c][:R], err_msg=f"valid {c}")
+        if ty == pp.STRING:
+            np.testing.assert_array_equal(out.str_end[c][:R].cpu().numpy(), ref.str_end[c][:R],
+                                          err_msg=f"end {c}")
+    return ref, out, res

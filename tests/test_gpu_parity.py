@@ -1,0 +1,216 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, bit-exact.
+
+Sizes span several 8 KiB tiles (and 4 KiB tiles for the 16-byte chunk
+option) with ragged tails; the edge cases cover empty input, inputs ending
+at and off tile boundaries, fields and quotes spanning tiles, a tile of
+nothing but delimiters, invalid input, unterminated quotes, capacity, an
+unaligned input pointer, 3- to 8-state DFAs, and hard float conversions.
+"""
+import random
+
+import numpy as np
+import pytest
+
+import datagen
+import paper_1905_13415_amd as pp
+from datagen import dialects as D
+from parity import assert_same, gpu_parse
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu,
+              pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
+
+TILE = 8192
+
+
+def u8(b):
+    return np.frombuffer(bytes(b), dtype=np.uint8)
+
+
+# ---- worked examples ---------------------------------------------------------------
+
+def test_quoted_example():
+    assert_same(u8(b'a,"b,c"\n"d""e",f\n'), D.paper6(), [D.STRING, D.STRING])
+
+
+def test_ragged_example():
+    for dfa in (D.paper6(), D.csv4()):
+        assert_same(u8(b"1,Apples\n2\n"), dfa, [D.INT64, D.STRING])
+
+
+# ---- edge cases ----------------------------------------------------------------------
+
+@pytest.mark.parametrize("text", [b"", b"a", b"\n", b",", b'"', b"1,2", b"1,", b"\n\n\n",
+                                  b'"abc', b'a"b\n', b'"a""', b",,,\n,,\n"])
+def test_tiny_inputs(text):
+    for dfa in (D.csv4(), D.paper6()):
+        assert_same(u8(text), dfa, [D.STRING, D.INT64, D.STRING])
+
+
+@pytest.mark.parametrize("n", [TILE - 1, TILE, TILE + 1, 2 * TILE, 3 * TILE + 17])
+def test_tile_boundaries(n):
+    g = datagen.c1()
+    data = g.data[:n].copy()
+    assert_same(data, D.csv4(), D.SCHEMA_C1.types)
+    # the same length ending in a record delimiter exactly at the boundary
+    data[-1] = ord("\n")
+    assert_same(data, D.csv4(), D.SCHEMA_C1.types)
+
+
+def test_all_delimiters():
+    """Every byte a delimiter: the per-tile staging at its maximum."""
+    for ch in (b",", b"\n"):
+        assert_same(u8(ch * (3 * TILE + 5)), D.csv4(), [D.INT64, D.STRING, D.FLOAT64])
+
+
+def test_long_quoted_field_spanning_tiles():
+    body = bytes(random.Random(1).choice(b'ab,\n ') for _ in range(5 * TILE))
+    data = b'1,"' + body + b'",2\n3,"x",4\n'
+    assert_same(u8(data), D.csv4(), [D.INT64, D.STRING, D.INT64])
+    assert_same(u8(data), D.paper6(), [D.INT64, D.STRING, D.INT64])
+
+
+def test_long_numeric_field_spanning_tiles():
+    data = b"7," + b"0" * (2 * TILE + 100) + b"42,x\n" + b"1.5," + b"9" * 30000 + b",y\n"
+    assert_same(u8(data), D.csv4(), [D.FLOAT64, D.INT64, D.STRING])
+
+
+def test_invalid_and_unterminated():
+    g = datagen.c1()
+    data = bytearray(g.data[:5 * TILE])
+    data[3 * TILE + 100] = ord('"')  # a quote in an unquoted field under paper6 -> INV
+    ref, _, res = assert_same(u8(data), D.paper6(), D.SCHEMA_C1.types)
+    assert res["status"] in (pp.RESULT_INVALID_INPUT, pp.RESULT_OK)
+    assert_same(u8(b'1,2\n3,"unterminated\n' + b"x" * (2 * TILE)), D.csv4(), [D.INT64, D.STRING])
+    assert_same(u8(b'1,2\n3,"unterminated\n' + b"x" * (2 * TILE)), D.paper6(), [D.INT64, D.STRING])
+
+
+def test_capacity_exceeded():
+    g = datagen.c1()
+    data = g.data[:6 * TILE]
+    assert_same(data, D.csv4(), D.SCHEMA_C1.types, cap_records=100, cap_fields=333)
+
+
+def test_unaligned_input():
+    g = datagen.c1()
+    for off in (1, 3, 8):
+        assert_same(g.data[:4 * TILE + 77], D.csv4(), D.SCHEMA_C1.types, offset=off)
+
+
+def test_chunk16_option():
+    g = datagen.c1()
+    assert_same(g.data[:200000], D.csv4(), D.SCHEMA_C1.types, opts=pp.options(16, 256))
+
+
+def test_ragged_and_extra_fields():
+    rnd = random.Random(5)
+    lines = []
+    for _ in range(5000):
+        k = rnd.randint(0, 12)
+        lines.append(",".join(str(rnd.randint(-99, 99)) for _ in range(k)))
+    data = ("\n".join(lines) + "\n").encode()
+    assert_same(u8(data), D.csv4(), [D.INT64] * 6)
+    assert_same(u8(data), D.csv4(), [])
+
+
+# ---- random symbol soup over each dialect ------------------------------------------------
+
+@pytest.mark.parametrize("name", ["csv4", "paper6", "log6", "s3", "s5", "s7", "s8"])
+def test_random_symbol_soup(name):
+    dfa = D.ALL_DFAS[name]()
+    alphabet = b"".join(dfa.group_symbols) + b"a1.-"
+    rnd = random.Random(hash(name) & 0xffff)
+    types = [D.STRING, D.INT64, D.FLOAT64, D.STRING, D.INT64]
+    for n in (100, 5000, 3 * TILE + 11):
+        data = bytes(rnd.choice(alphabet) for _ in range(n))
+        assert_same(u8(data), dfa, types)
+
+
+# ---- workloads ------------------------------------------------------------------------------
+
+def test_c1_full():
+    g = datagen.c1()
+    assert_same(g.data, D.csv4(), D.SCHEMA_C1.types)
+    assert_same(g.data, D.paper6(), D.SCHEMA_C1.types)
+
+
+def test_c2_c3_slices():
+    assert_same(datagen.c2(nbytes=24 << 20).data, D.csv4(), D.SCHEMA_C2.types)
+    assert_same(datagen.c3(nbytes=40 << 20).data, D.csv4(), D.SCHEMA_C3.types)
+
+
+@pytest.mark.parametrize("name,delim,qstyle", [("csv4", b"\t", 1), ("s5", b"|", 1), ("s3", b",", 3),
+                                               ("s7", b",", 2), ("paper6", b",", 1)])
+def test_mixed_dialects(name, delim, qstyle):
+    dfa = D.ALL_DFAS[name](delim) if name != "paper6" else D.paper6()
+    g = datagen.mixed(17, 3 << 20, delim=delim, qstyle=qstyle)
+    assert_same(g.data, dfa, D.SCHEMA_C1.types)
+
+
+def test_log_dialects():
+    g = datagen.log(23, 3 << 20)
+    assert_same(g.data, D.log6(), D.SCHEMA_LOG12.types)
+    assert_same(g.data, D.s8(), D.SCHEMA_LOG12.types)
+
+
+# ---- conversions ------------------------------------------------------------------------------
+
+HARD_FLOATS = ["0", "-0.0", "1e10", "1E-5", "+3.25e+2", "0.1", "9007199254740993", "1e308", "1.8e308",
+               "-1e400", "4.9406564584124654e-324", "2.4703282292062327e-324",
+               "2.4703282292062328e-324", "1e-320", "2.2250738585072011e-308",
+               "1.7976931348623157e308", "1.00000000000000011102230246251565404236316680908203125",
+               "1.00000000000000011102230246251565404236316680908203124",
+               "1.00000000000000011102230246251565404236316680908203126",
+               "12345678901234567890123", "0.000000000000000000000000000000123456789",
+               "123456789012345678901234567890e-10", "7.2057594037927933e16", "3.14159265358979323846264338",
+               ".5", "5.", "", ".", "e5", "1e", "1e+", "--1", "inf", "nan", "1,0", "0x1p3",
+               "1" * 400 + "e-400", "0." + "0" * 330 + "1", "179769313486231580793728971405301e276",
+               "2.225073858507201136057409796709131975934819546351645648e-308"]
+
+
+def test_hard_floats():
+    rnd = random.Random(3)
+    vals = list(HARD_FLOATS)
+    for _ in range(4000):
+        digits = "".join(rnd.choice("0123456789") for _ in range(rnd.randint(1, 25)))
+        point = rnd.randint(0, len(digits))
+        vals.append(digits[:point] + "." + digits[point:] + f"e{rnd.randint(-330, 310)}")
+    data = "".join(f"{v},{i}\n" for i, v in enumerate(vals)).encode().replace(b",,", b",")
+    data = "".join(f'"{v}",{i}\n' for i, v in enumerate(vals)).encode()
+    assert_same(u8(data), D.csv4(), [D.FLOAT64, D.INT64])
+
+
+INTS = ["0", "-0", "+7", "9223372036854775807", "-9223372036854775808", "9223372036854775808",
+        "-9223372036854775809", "00000000000000000000042", "", "+", "-", "1 ", " 1", "1.0", "12a",
+        "99999999999999999999"]
+TIMES = ["1970-01-01 00:00:00", "1969-12-31 23:59:59", "2000-02-29 12:00:00", "1900-02-29 00:00:00",
+         "2001-02-29 00:00:00", "2018-13-01 00:00:00", "0001-01-01T00:00:00", "9999-12-31 23:59:59",
+         "2018-01-01 24:00:00", "2018-01-01 00:00:60", "2018-01-01 00:00", "2018/01/01 00:00:00"]
+DATES = ["1970-01-01", "1600-02-29", "1700-02-29", "2024-02-29", "2023-02-29", "2019-04-31", "0000-03-01",
+         "2019-4-30", "20190430"]
+
+
+def test_int_time_date_edge_cases():
+    k = max(len(INTS), len(TIMES), len(DATES))
+    rows = []
+    for i in range(k):
+        rows.append(",".join([INTS[i % len(INTS)], TIMES[i % len(TIMES)], DATES[i % len(DATES)]]))
+    data = ("\n".join(rows) + "\n").encode()
+    assert_same(u8(data), D.csv4(), [D.INT64, D.TIMESTAMP_S, D.DATE_DAYS])
+
+
+def test_all_days_date_column():
+    import datetime
+    d0 = datetime.date(1600, 1, 1)
+    data = "\n".join((d0 + datetime.timedelta(days=i)).isoformat() for i in range(300000)).encode()
+    assert_same(u8(data), D.csv4(), [D.DATE_DAYS])
+
+
+def test_repeated_runs_identical():
+    g = datagen.c2(nbytes=8 << 20)
+    out1, r1 = gpu_parse(g.data, D.csv4(), D.SCHEMA_C2.types)
+    out2, r2 = gpu_parse(g.data, D.csv4(), D.SCHEMA_C2.types)
+    assert r1 == r2
+    assert torch.equal(out1.field_offsets, out2.field_offsets)
+    for a, b in zip(out1.values, out2.values):
+        assert torch.equal(a.view(torch.int64), b.view(torch.int64))
