@@ -144,7 +144,7 @@ def main():
             "workload": "c2: 1 GiB numeric CSV, 18 columns (4 int64, 2 timestamp, 8 float64, 4 string), "
                         "~130 B/record, csv4 DFA, plain single-buffer launch",
             "bytes": n, "records": R, "fields": F,
-            "bytes_per_thread": args.bytes_per_thread or 32, "block_threads": 256,
+            "bytes_per_thread": args.bytes_per_thread or 64, "block_threads": 512 if not args.bytes_per_thread else 256,
         },
         "kernel_ms": {"mean": round(ms_mean, 4), "median": round(ms_med, 4), "min": round(per[0], 4),
                       "max": round(per[-1], 4)},

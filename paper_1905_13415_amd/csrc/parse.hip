@@ -1,39 +1,48 @@
 // Single-pass parallel parse of delimiter-separated text on gfx950.
 //
 // One workgroup of NT threads owns a tile of NT*B input bytes; each thread
-// owns a chunk of B bytes (Sec. 3.1 chunks). Per tile, in one kernel:
-//   1. stage the tile in LDS with 16-byte loads;
+// owns a chunk of B bytes (the per-thread chunks of Sec. 3.1). Per tile, in
+// one kernel:
+//   1. stage the tile in LDS with 16-byte loads; every thread keeps its
+//      chunk in registers;
 //   2. multi-state pass (Sec. 3.1): per chunk, one DFA instance per state,
 //      packed one byte per state in a register; a step is one v_perm_b32
 //      (<= 4 states) or two (<= 8 states) that looks every instance up in
-//      the byte's transition row: the state-transition vector;
-//   3. exclusive composition scan (Sec. 3.1, (a o b)_i = b[a_i]): wave scan
-//      by shuffles, block scan through LDS, device scan by decoupled
-//      lookback over per-tile words (single-pass scan, Sec. 2);
-//   4. tag pass from the chunk's start state: register bitmaps of record
+//      the byte's transition row: the chunk's state-transition vector;
+//   3. exclusive composition scan ((a o b)_i = b[a_i], Sec. 3.1): wave scan
+//      by shuffles, block scan through LDS, device scan by decoupled lookback
+//      (the single-pass scan the paper builds on, Sec. 2) in which one
+//      wavefront polls 64 predecessor tiles at a time;
+//   4. tag pass from the chunk's start state into register bitmaps of record
 //      delimiters, field delimiters and control symbols (Sec. 3.1);
-//   5. record counts (+), field counts (+) and column carries (the abs/rel
-//      operator of Sec. 3.2) scanned the same way, one lookback word each;
-//   6. delimiter positions staged in LDS, then written coalesced as
-//      field_offsets / record_offsets; column ids written per delimiter;
-//   7. conversion (Sec. 3.3): the tile's fields are visited column-major,
-//      (column, record) pairs, so a wavefront converts one column's type and
-//      its stores to that typed column are contiguous. This replaces the
-//      paper's radix-sort partition by column: the pair addresses the slot.
+//   5. record counts (+), field counts (+), column carries (the abs/rel
+//      operator of Sec. 3.2) and the last delimiter position, scanned the
+//      same way;
+//   6. delimiter positions staged in LDS and written coalesced as field and
+//      record offsets; column ids written per delimiter;
+//   7. typed conversion (Sec. 3.3): the tile's (column, record) pairs are
+//      visited column-major, so a wavefront converts one column's type and
+//      its stores into that typed column are contiguous. This takes the place
+//      of the paper's radix-sort partition by column tag: the pair addresses
+//      the output slot directly.
+// Tiles with more fields or records than the LDS staging holds take a
+// per-thread path for steps 6-7 that gives the same outputs.
 // The input is read from HBM once; per-symbol metadata never leaves the chip.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
 #include <cstring>
+#include <type_traits>
 
 #include "convert.h"
 #include "parparaw.h"
 
 namespace pp {
 
-constexpr int kTagControl = 1;
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned long long u64;
+constexpr uint32_t kTagControl = 1;
 
 struct ColDesc {
     void* values;
@@ -50,8 +59,8 @@ struct Params {
     int64_t* field_offsets;
     int32_t* column_ids;
     pp_result_t* result;
-    unsigned long long* words;  // kWordsPerTile per tile
-    unsigned int* counter;      // tile ticket
+    u64* words;             // kWordsPerTile per tile
+    unsigned int* counter;  // tile ticket
     int32_t num_tiles;
     int32_t ncols;
     int32_t num_states;
@@ -66,29 +75,46 @@ struct Params {
 };
 
 // ---- lookback words ----------------------------------------------------------
-// Each word is self-contained: [status:2 | payload:62], published and polled
-// with relaxed agent-scope atomics (no ordering with other memory is needed).
-constexpr int kWordsPerTile = 5;
-enum { W_STATE = 0, W_REC = 1, W_FLD = 2, W_COL = 3, W_LAST = 4 };
-constexpr unsigned long long kAgg = 1ull << 62, kIncl = 2ull << 62;
-constexpr unsigned long long kPayload = (1ull << 62) - 1;
-constexpr unsigned long long kColAbs = 1ull << 61;
-constexpr unsigned long long kColVal = kColAbs - 1;
-// W_LAST payload: has:1 @61 | ctl_last:1 @60 | state_after:4 @56 | pos:56
-constexpr unsigned long long kLastHas = 1ull << 61, kLastCtl = 1ull << 60;
-constexpr unsigned long long kLastPos = (1ull << 56) - 1;
+// Every word is self-contained, [status:2 | payload:62], written once per
+// state by relaxed agent-scope atomics, so no ordering with other memory is
+// needed. Aggregates and inclusive prefixes of the counts live in separate
+// words: an aggregate is never overwritten, so a reader always finds either
+// all four inclusive words or both aggregate words of a tile.
+constexpr int kWordsPerTile = 8;
+enum { W_STATE = 0, W_AGG0 = 1, W_AGG1 = 2, W_IREC = 3, W_IFLD = 4, W_ICOL = 5, W_ILAST = 6 };
+constexpr u64 kAgg = 1ull << 62, kIncl = 2ull << 62;
+constexpr u64 kPayload = (1ull << 62) - 1;
+// inclusive payloads: col = abs:1 @61 | value; last = has:1 @61 | ctl:1 @60 |
+// state after the delimiter:4 @56 | absolute position:56
+constexpr u64 kColAbs = 1ull << 61;
+constexpr u64 kColVal = kColAbs - 1;
+constexpr u64 kLastHas = 1ull << 61, kLastCtl = 1ull << 60;
+constexpr u64 kLastPos = (1ull << 56) - 1;
 
-__device__ inline void publish(unsigned long long* w, unsigned long long v)
+__device__ inline void publish(u64* w, u64 v)
 {
     __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-__device__ inline unsigned long long poll(unsigned long long* w)
+__device__ inline u64 peek(u64* w)
 {
-    unsigned long long v;
-    while (((v = __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) >> 62) == 0)
-        __builtin_amdgcn_s_sleep(1);
-    return v;
+    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ inline u64 ballot(bool x) { return __ballot(x); }
+
+__device__ inline u64 shfl_down64(u64 v, int d)
+{
+    uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)v, d);
+    uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)(v >> 32), d);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ inline u64 readlane0_64(u64 v)
+{
+    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return ((u64)hi << 32) | lo;
 }
 
 // ---- state-transition vectors (Sec. 3.1) --------------------------------------
@@ -106,7 +132,7 @@ __device__ inline SV<NS8> sv_identity()
 }
 
 // (a o b)_i = b[a_i]: v_perm_b32 picks byte sel of {src0:src1}, bytes 0-3
-// from src1, 4-7 from src0.
+// from src1 and 4-7 from src0.
 template <bool NS8>
 __device__ inline SV<NS8> compose(SV<NS8> a, SV<NS8> b)
 {
@@ -157,10 +183,20 @@ __device__ inline SV<NS8> shfl_up_sv(SV<NS8> v, int d)
     return r;
 }
 
-// ---- count scan element (Sec. 3.2) ----------------------------------------------
-// records, delimiters (fields closed), column carry (bit 31 = abs).
+template <bool NS8>
+__device__ inline SV<NS8> shfl_down_sv(SV<NS8> v, int d)
+{
+    SV<NS8> r;
+    r.lo = (uint32_t)__shfl_down((int)v.lo, d);
+    r.hi = NS8 ? (uint32_t)__shfl_down((int)v.hi, d) : 0u;
+    return r;
+}
+
+// ---- count scan element within a tile (Sec. 3.2) ---------------------------------
+// nr: record delimiters; nf: delimiters (fields closed); col: column carry,
+// bit 31 = abs; last: tile-relative position + 1 of the last delimiter (0: none).
 struct Cnt {
-    uint32_t nr, nf, col;
+    uint32_t nr, nf, col, last;
 };
 constexpr uint32_t kCAbs = 1u << 31;
 
@@ -169,14 +205,52 @@ __device__ inline Cnt cnt_combine(Cnt a, Cnt b)
     Cnt r;
     r.nr = a.nr + b.nr;
     r.nf = a.nf + b.nf;
-    r.col = (b.col & kCAbs) ? b.col : a.col + b.col;  // Sec. 3.2 abs/rel operator
+    r.col = (b.col & kCAbs) ? b.col : a.col + b.col;  // the abs/rel operator of Sec. 3.2
+    r.last = b.last ? b.last : a.last;
     return r;
 }
 
 __device__ inline Cnt shfl_up_cnt(Cnt c, int d)
 {
     return {(uint32_t)__shfl_up((int)c.nr, d), (uint32_t)__shfl_up((int)c.nf, d),
-            (uint32_t)__shfl_up((int)c.col, d)};
+            (uint32_t)__shfl_up((int)c.col, d), (uint32_t)__shfl_up((int)c.last, d)};
+}
+
+// ---- device-wide count prefix ------------------------------------------------------
+struct Tot {
+    u64 rec, fld, col, last;
+};
+
+__device__ inline Tot tot_combine(Tot a, Tot b)
+{
+    Tot r;
+    r.rec = a.rec + b.rec;
+    r.fld = a.fld + b.fld;
+    r.col = (b.col & kColAbs) ? b.col : a.col + b.col;
+    const u64 body = (b.last & kLastHas) ? b.last : a.last;
+    r.last = (body & ~kLastCtl) | (b.last & kLastCtl);  // control bit of the last byte: from b
+    return r;
+}
+
+__device__ inline Tot shfl_down_tot(Tot t, int d)
+{
+    return {shfl_down64(t.rec, d), shfl_down64(t.fld, d), shfl_down64(t.col, d), shfl_down64(t.last, d)};
+}
+
+// aggregate words: agg0 = nr:31 @31 | nf:31; agg1 = col:31 @31 | last:31 where
+// col = abs:1 @30 | value:30 and last = has:1 @30 | ctl:1 @29 | state after:4 @25 | pos in tile:25
+__device__ inline Tot tot_from_agg(u64 a0, u64 a1, int64_t tile_start)
+{
+    Tot t;
+    t.rec = (a0 >> 31) & 0x7fffffffull;
+    t.fld = a0 & 0x7fffffffull;
+    const u64 c = (a1 >> 31) & 0x7fffffffull;
+    t.col = ((c >> 30) & 1 ? kColAbs : 0ull) | (c & 0x3fffffffull);
+    const u64 l = a1 & 0x7fffffffull;
+    t.last = ((l >> 29) & 1) ? kLastCtl : 0ull;
+    if ((l >> 30) & 1)
+        t.last |= kLastHas | (((l >> 25) & 0xfull) << 56) | (u64)(tile_start + (int64_t)(l & 0x1ffffffull));
+    return t;
 }
 
 // Reads input bytes for conversion: from the LDS tile when inside it, from
@@ -198,40 +272,93 @@ __device__ inline int64_t wave_sum(int64_t v)
     return v;
 }
 
+// Strip the enclosing control symbols of field [b, e) and convert it into
+// column c, record rec. ctl_first/ctl_last_sym: whether bytes b and e-1 are
+// control symbols. Returns 1 on a conversion error.
+__device__ inline int store_field(const Params& p, const ByteSrc& src, int c, int ty, int64_t rec,
+                                  int64_t b, int64_t e, bool ctl_first, bool ctl_last_sym)
+{
+    int64_t begin = b, end = e;
+    if (end > begin && ctl_first) ++begin;
+    if (end - 1 >= begin && ctl_last_sym) --end;
+    const bool store = rec < p.cap_records;
+    const ColDesc cd = p.cols[c];
+    if (ty == PP_STRING) {
+        if (store) {
+            ((int64_t*)cd.values)[rec] = begin;
+            cd.str_end[rec] = end;
+            cd.valid[rec] = 1;
+        }
+        return 0;
+    }
+    if (end == begin) {  // empty: the column default, not an error (Sec. 4.3)
+        if (store) {
+            ((int64_t*)cd.values)[rec] = 0;
+            cd.valid[rec] = 0;
+        }
+        return 0;
+    }
+    bool ok;
+    u64 bits;
+    if (ty == PP_FLOAT64) {
+        double dv = 0.0;
+        ok = conv_float64(src, begin, end, &dv);
+        bits = ok ? __builtin_bit_cast(u64, dv) : 0ull;
+    } else {
+        int64_t iv = 0;
+        if (ty == PP_INT64) ok = conv_int64(src, begin, end, &iv);
+        else if (ty == PP_TIMESTAMP_S) ok = conv_timestamp(src, begin, end, &iv);
+        else ok = conv_date(src, begin, end, &iv);
+        bits = ok ? (u64)iv : 0ull;
+    }
+    if (store) {
+        ((u64*)cd.values)[rec] = bits;
+        cd.valid[rec] = ok;
+    }
+    return !ok;
+}
+
+__device__ inline void store_missing(const Params& p, int c, int ty, int64_t rec)
+{
+    if (rec >= p.cap_records || ty == PP_SKIP) return;
+    const ColDesc cd = p.cols[c];
+    ((u64*)cd.values)[rec] = 0;  // 0 and 0.0 share the bit pattern
+    cd.valid[rec] = 0;
+    if (ty == PP_STRING) cd.str_end[rec] = 0;
+}
+
 // ---- the kernel ---------------------------------------------------------------
 template <int NT, int B, bool NS8>
 __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 {
-    static_assert(B == 16 || B == 32, "chunk bitmaps are one dword");
+    static_assert(B == 16 || B == 32 || B == 64, "chunk bitmaps are one or two dwords");
+    using M = std::conditional_t<(B > 32), u64, uint32_t>;
     constexpr int TILE = NT * B;
     constexpr int NW = NT / 64;
+    constexpr int FCAP = TILE / 2;   // delimiters staged per tile
+    constexpr int RCAP = TILE / 16;  // records staged per tile
     static_assert(TILE <= 32768, "u16 positions");
 
     __shared__ uint32_t s_tnext[NS8 ? 512 : 256];  // byte -> next state of every state
     __shared__ uint32_t s_tcomb[NS8 ? 512 : 256];  // byte -> per state (next*8 | tag<<6)
     __shared__ __align__(16) uint8_t s_bytes[TILE];
-    __shared__ uint16_t s_pos[TILE + 2];     // tile-relative delimiter positions
-    __shared__ uint16_t s_recend[TILE + 2];  // local field index of each record delimiter
-    __shared__ uint32_t s_ctl[TILE / 32];    // control-symbol bitmap of the tile
+    __shared__ uint16_t s_pos[FCAP];     // tile-relative delimiter positions
+    __shared__ uint16_t s_recend[RCAP];  // local field index of each record delimiter
+    __shared__ uint32_t s_ctl[TILE / 32];  // control-symbol bitmap of the tile
     __shared__ uint8_t s_types[PP_MAX_COLUMNS];
     __shared__ SV<NS8> s_wsv[NW];
     __shared__ Cnt s_wcnt[NW];
-    __shared__ uint32_t s_tile;
-    __shared__ uint32_t s_s0;
-    __shared__ unsigned long long s_pref[4];
+    __shared__ uint32_t s_tile, s_s0, s_final, s_last_sa, s_ctl_last;
     __shared__ int s_lasttid;
-    __shared__ uint32_t s_last_sa;
-    __shared__ unsigned long long s_last_pos;
-    __shared__ uint32_t s_ctl_last;
-    __shared__ uint32_t s_final;
-    __shared__ unsigned long long s_err, s_ragged;
+    __shared__ u64 s_pref[4];
+    __shared__ u64 s_err, s_ragged;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
 
     if (tid == 0) {
-        s_tile = atomicAdd(p.counter, 1u);
+        s_tile = atomicAdd(p.counter, 1u);  // tiles in start order: predecessors are running
         s_lasttid = -1;
         s_err = 0;
         s_ragged = 0;
@@ -263,6 +390,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     const int64_t n = p.n;
     const int64_t tile_start = (int64_t)tile * TILE;
     const int tile_len = (int)(n - tile_start < TILE ? n - tile_start : TILE);
+    u64* const tw = p.words + (size_t)tile * kWordsPerTile;
 
     // ---- 1. stage the tile --------------------------------------------------------
     {
@@ -293,26 +421,20 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 
     // ---- 2. multi-state pass ----------------------------------------------------------
     SV<NS8> vec = sv_identity<NS8>();
+    auto mstep = [&](int i) {
+        const uint32_t b = byte_at(i);
+        SV<NS8> t;
+        if constexpr (NS8) { t.lo = s_tnext[2 * b]; t.hi = s_tnext[2 * b + 1]; }
+        else { t.lo = s_tnext[b]; t.hi = 0; }
+        vec = compose(vec, t);
+    };
     if (len == B) {
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
-            const uint32_t b = byte_at(i);
-            SV<NS8> t;
-            if constexpr (NS8) { t.lo = s_tnext[2 * b]; t.hi = s_tnext[2 * b + 1]; }
-            else { t.lo = s_tnext[b]; t.hi = 0; }
-            vec = compose(vec, t);
-        }
+        for (int i = 0; i < B; ++i) mstep(i);
     } else {
 #pragma unroll
-        for (int i = 0; i < B; ++i) {
-            if (i < len) {
-                const uint32_t b = byte_at(i);
-                SV<NS8> t;
-                if constexpr (NS8) { t.lo = s_tnext[2 * b]; t.hi = s_tnext[2 * b + 1]; }
-                else { t.lo = s_tnext[b]; t.hi = 0; }
-                vec = compose(vec, t);
-            }
-        }
+        for (int i = 0; i < B; ++i)
+            if (i < len) mstep(i);
     }
 
     // ---- 3. composition scan ------------------------------------------------------------
@@ -330,34 +452,58 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     if (lane == 0) ex = sv_identity<NS8>();
     ex = compose(wpre, ex);  // exclusive prefix of this chunk within the tile
 
-    unsigned long long* tw = p.words + (size_t)tile * kWordsPerTile;
-    if (tid == 0) {
+    if (wave == 0) {
         SV<NS8> agg = sv_identity<NS8>();
         for (int w = 0; w < NW; ++w) agg = compose(agg, s_wsv[w]);
         SV<NS8> pre = sv_identity<NS8>();
         if (tile == 0) {
-            publish(tw + W_STATE, kIncl | sv_to_nib(agg));
+            if (lane == 0) publish(tw + W_STATE, kIncl | sv_to_nib(agg));
         } else {
-            publish(tw + W_STATE, kAgg | sv_to_nib(agg));
+            if (lane == 0) publish(tw + W_STATE, kAgg | sv_to_nib(agg));
+            // one wavefront polls 64 predecessors per step
             SV<NS8> acc = sv_identity<NS8>();
-            for (int64_t j = (int64_t)tile - 1;; --j) {
-                unsigned long long v = poll(p.words + (size_t)j * kWordsPerTile + W_STATE);
-                acc = compose(sv_from_nib<NS8>((uint32_t)v), acc);
-                if ((v >> 62) == 2) break;
+            for (int64_t base = (int64_t)tile - 1;; base -= 64) {
+                const int64_t j = base - lane;
+                u64 v = j >= 0 ? peek(p.words + (size_t)j * kWordsPerTile + W_STATE) : kIncl;
+                int first;
+                for (;;) {
+                    const u64 inc = ballot((v >> 62) == 2);
+                    const u64 rdy = ballot((v >> 62) != 0);
+                    first = inc ? __ffsll((long long)inc) - 1 : 64;
+                    const u64 need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+                    if ((rdy & need) == need) break;
+                    __builtin_amdgcn_s_sleep(1);
+                    if ((v >> 62) == 0) v = peek(p.words + (size_t)j * kWordsPerTile + W_STATE);
+                }
+                // ordered reduction, earlier tiles (higher lanes) on the left
+                SV<NS8> x = lane <= first ? sv_from_nib<NS8>((uint32_t)v) : sv_identity<NS8>();
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    SV<NS8> y = shfl_down_sv(x, d);
+                    if ((lane & (2 * d - 1)) == 0) x = compose(y, x);
+                }
+                SV<NS8> w;
+                w.lo = __builtin_amdgcn_readfirstlane(x.lo);
+                w.hi = __builtin_amdgcn_readfirstlane(x.hi);
+                acc = compose(w, acc);
+                if (first < 64) break;
             }
             pre = acc;
-            publish(tw + W_STATE, kIncl | sv_to_nib(compose(acc, agg)));
+            if (lane == 0) publish(tw + W_STATE, kIncl | sv_to_nib(compose(acc, agg)));
         }
-        s_s0 = sv_get(pre, (uint32_t)p.start_state);
-        s_final = sv_get(compose(pre, agg), (uint32_t)p.start_state);
+        if (lane == 0) {
+            s_s0 = sv_get(pre, (uint32_t)p.start_state);
+            s_final = sv_get(compose(pre, agg), (uint32_t)p.start_state);
+        }
     }
     __syncthreads();
     const uint32_t s_start = sv_get(ex, s_s0);
 
     // ---- 4. tag pass ----------------------------------------------------------------------
     // x = tcomb[b] >> (8*state): bits 3-5 next state * 8, bit 6 tag bit 0, bit 7 tag bit 1.
-    uint32_t p0 = 0, p1 = 0, s8 = s_start * 8u;
-    auto step = [&](int i) {
+    M p0 = 0, p1 = 0;
+    uint32_t s8 = s_start * 8u;
+    auto tstep = [&](int i) {
         const uint32_t b = byte_at(i);
         uint32_t x;
         if constexpr (NS8) {
@@ -367,19 +513,19 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
             x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
         }
         s8 = x & 0x38u;
-        p0 |= ((x >> 6) & 1u) << i;
-        p1 |= (x >> 7) << i;
+        p0 |= (M)((x >> 6) & 1u) << i;
+        p1 |= (M)(x >> 7) << i;
     };
     if (len == B) {
 #pragma unroll
-        for (int i = 0; i < B; ++i) step(i);
+        for (int i = 0; i < B; ++i) tstep(i);
     } else {
 #pragma unroll
         for (int i = 0; i < B; ++i)
-            if (i < len) step(i);
+            if (i < len) tstep(i);
     }
     const uint32_t s_end = s8 >> 3;
-    const uint32_t dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
+    const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
     const int64_t cstart = tile_start + c0;
     const bool holds_last = len > 0 && cstart + len == n;
     const uint32_t vend = holds_last && !((rmask >> (len - 1)) & 1u);  // end of input closes a record
@@ -388,8 +534,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     if (p.invalid_state >= 0 && s_start != (uint32_t)p.invalid_state && s_end == (uint32_t)p.invalid_state) {
         uint32_t s = s_start;
         for (int i = 0; i < len; ++i) {
-            const uint32_t g = p.group_of[s_bytes[c0 + i]];
-            const uint32_t nx = p.next[g][s];
+            const uint32_t nx = p.next[p.group_of[s_bytes[c0 + i]]][s];
             if (nx == (uint32_t)p.invalid_state) {
                 p.result->first_invalid_offset = cstart + i;
                 break;
@@ -398,20 +543,32 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         }
     }
 
+    auto popc = [](M m) -> uint32_t {
+        if constexpr (B > 32) return (uint32_t)__popcll(m);
+        else return (uint32_t)__popc(m);
+    };
+    auto msb = [](M m) -> int {
+        if constexpr (B > 32) return 63 - __clzll((long long)m);
+        else return 31 - __clz((int)m);
+    };
     Cnt mine;
-    mine.nr = __popc(rmask) + vend;
-    mine.nf = __popc(dmask) + vend;
+    mine.nr = popc(rmask) + vend;
+    mine.nf = popc(dmask) + vend;
     if (rmask | vend) {
         uint32_t after = 0;
         if (!vend) {
-            const int hb = 31 - __clz(rmask);
-            after = hb == 31 ? 0u : __popc(dmask & ~rmask & (~0u << (hb + 1)));
+            const int hb = msb(rmask);
+            after = hb == B - 1 ? 0u : popc(dmask & ~rmask & (~(M)0 << (hb + 1)));
         }
         mine.col = kCAbs | after;
     } else {
-        mine.col = __popc(dmask);
+        mine.col = popc(dmask);
     }
-    if constexpr (B == 32) {
+    mine.last = vend ? (uint32_t)(tile_len + 1) : (dmask ? (uint32_t)(c0 + msb(dmask) + 1) : 0u);
+    if constexpr (B == 64) {
+        s_ctl[2 * tid] = (uint32_t)cmask;
+        s_ctl[2 * tid + 1] = (uint32_t)(cmask >> 32);
+    } else if constexpr (B == 32) {
         s_ctl[tid] = cmask;
     } else {  // two 16-byte chunks per bitmap word
         const uint32_t part = cmask << ((tid & 1) * 16);
@@ -429,223 +586,251 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     if (lane == 63) s_wcnt[wave] = cin;
     if (mine.nf) atomicMax(&s_lasttid, tid);
     __syncthreads();
-    Cnt cpre = {0u, 0u, 0u};
+    Cnt cpre = {0u, 0u, 0u, 0u};
     for (int w = 0; w < wave; ++w) cpre = cnt_combine(cpre, s_wcnt[w]);
     Cnt cex = shfl_up_cnt(cin, 1);
-    if (lane == 0) cex = {0u, 0u, 0u};
+    if (lane == 0) cex = {0u, 0u, 0u, 0u};
     cex = cnt_combine(cpre, cex);
+    Cnt tagg = {0u, 0u, 0u, 0u};
+    for (int w = 0; w < NW; ++w) tagg = cnt_combine(tagg, s_wcnt[w]);
 
-    // position of the tile's last delimiter and the state after it, found by
-    // the chunk that holds it (a virtual end-of-input delimiter sits at n)
+    // state after the tile's last delimiter, from the chunk that holds it
     if (tid == s_lasttid) {
         uint32_t sa = 0;
-        int64_t pos = n;
         if (!vend) {
-            const int hb = 31 - __clz(dmask);
+            const int hb = msb(dmask);
             uint32_t s = s_start;
             for (int i = 0; i <= hb; ++i) s = p.next[p.group_of[s_bytes[c0 + i]]][s];
             sa = s;
-            pos = cstart + hb;
         }
         s_last_sa = sa;
-        s_last_pos = (unsigned long long)pos;
     }
-    if (len > 0 && c0 + len == tile_len) s_ctl_last = (cmask >> (len - 1)) & 1u;
+    if (len > 0 && c0 + len == tile_len) s_ctl_last = (uint32_t)((cmask >> (len - 1)) & 1u);
     __syncthreads();
 
-    if (tid < 4) {
-        Cnt agg = {0u, 0u, 0u};
-        for (int w = 0; w < NW; ++w) agg = cnt_combine(agg, s_wcnt[w]);
-        unsigned long long a;
-        if (tid == 0) a = agg.nr;
-        else if (tid == 1) a = agg.nf;
-        else if (tid == 2) a = (agg.col & kCAbs) ? (kColAbs | (agg.col & ~kCAbs)) : agg.col;
-        else {
-            a = s_ctl_last ? kLastCtl : 0ull;
-            if (s_lasttid >= 0)
-                a |= kLastHas | ((unsigned long long)s_last_sa << 56) | (s_last_pos & kLastPos);
-        }
-        auto comb = [&](unsigned long long x, unsigned long long y) -> unsigned long long {
-            if (tid <= 1) return (x + y) & kPayload;
-            if (tid == 2) return (y & kColAbs) ? y : ((x + y) & kPayload);
-            // last delimiter: the later one wins; control bit of the last byte from y
-            unsigned long long r = (y & kLastHas) ? (y & ~kLastCtl) : (x & ~kLastCtl);
-            return r | (y & kLastCtl);
-        };
-        unsigned long long seed = tid == 2 ? kColAbs : 0ull;
-        unsigned long long* wp = tw + W_REC + tid;
-        unsigned long long pre;
-        if (tile == 0) {
-            pre = seed;
-            publish(wp, kIncl | comb(seed, a));
-        } else {
-            publish(wp, kAgg | a);
-            unsigned long long acc = 0;  // identity of every operator: rel 0, no delimiter
-            bool first = true;
-            for (int64_t j = (int64_t)tile - 1;; --j) {
-                unsigned long long v = poll(p.words + (size_t)j * kWordsPerTile + W_REC + tid);
-                unsigned long long val = v & kPayload;
-                acc = first ? val : comb(val, acc);
-                first = false;
-                if ((v >> 62) == 2) break;
+    if (wave == 0) {
+        // this tile's aggregate, in the device representation
+        const uint32_t lastrel = tagg.last;  // position + 1, 0 = none
+        const u64 a0 = ((u64)tagg.nr << 31) | tagg.nf;
+        const u64 colw = (tagg.col & kCAbs) ? ((1ull << 30) | (tagg.col & ~kCAbs)) : tagg.col;
+        u64 lastw = s_ctl_last ? (1ull << 29) : 0ull;
+        if (lastrel) lastw |= (1ull << 30) | ((u64)s_last_sa << 25) | (u64)(lastrel - 1);
+        const u64 a1 = (colw << 31) | lastw;
+        const Tot mineT = tot_from_agg(a0, a1, tile_start);
+        Tot pre = {0ull, 0ull, kColAbs, 0ull};  // seed: record 0, field 0, column (abs, 0)
+        if (tile > 0) {
+            if (lane == 0) {
+                publish(tw + W_AGG0, kAgg | a0);
+                publish(tw + W_AGG1, kAgg | a1);
+            }
+            bool have = false;
+            Tot acc;
+            for (int64_t base = (int64_t)tile - 1;; base -= 64) {
+                const int64_t j = base - lane;
+                u64* pw = p.words + (size_t)(j >= 0 ? j : 0) * kWordsPerTile;
+                u64 ir = 0, iF = 0, ic = 0, il = 0, g0 = 0, g1 = 0;
+                bool incl_ok = false, agg_ok = false;
+                int first;
+                for (;;) {
+                    if (j >= 0 && !incl_ok) {
+                        ir = peek(pw + W_IREC); iF = peek(pw + W_IFLD);
+                        ic = peek(pw + W_ICOL); il = peek(pw + W_ILAST);
+                        incl_ok = (ir >> 62) && (iF >> 62) && (ic >> 62) && (il >> 62);
+                        if (!incl_ok && !agg_ok) {
+                            g0 = peek(pw + W_AGG0); g1 = peek(pw + W_AGG1);
+                            agg_ok = (g0 >> 62) && (g1 >> 62);
+                        }
+                    }
+                    if (j < 0) incl_ok = true;  // before tile 0: the seed (never reached)
+                    const u64 inc = ballot(incl_ok);
+                    const u64 rdy = ballot(incl_ok || agg_ok);
+                    first = inc ? __ffsll((long long)inc) - 1 : 64;
+                    const u64 need = first >= 63 ? ~0ull : ((2ull << first) - 1);
+                    if ((rdy & need) == need) break;
+                    __builtin_amdgcn_s_sleep(1);
+                }
+                Tot x;
+                if (lane > first) x = {0ull, 0ull, 0ull, 0ull};
+                else if (incl_ok) x = {ir & kPayload, iF & kPayload, ic & kPayload, il & kPayload};
+                else x = tot_from_agg(g0, g1, (int64_t)j * TILE);
+                if (j < 0) x = {0ull, 0ull, kColAbs, 0ull};
+#pragma unroll
+                for (int d = 1; d < 64; d <<= 1) {
+                    Tot y = shfl_down_tot(x, d);
+                    if ((lane & (2 * d - 1)) == 0) x = tot_combine(y, x);
+                }
+                Tot w = {readlane0_64(x.rec), readlane0_64(x.fld), readlane0_64(x.col), readlane0_64(x.last)};
+                acc = have ? tot_combine(w, acc) : w;
+                have = true;
+                if (first < 64) break;
             }
             pre = acc;
-            publish(wp, kIncl | comb(acc, a));
         }
-        s_pref[tid] = pre;
+        const Tot inc = tot_combine(pre, mineT);
+        if (lane == 0) {
+            publish(tw + W_IREC, kIncl | inc.rec);
+            publish(tw + W_IFLD, kIncl | inc.fld);
+            publish(tw + W_ICOL, kIncl | inc.col);
+            publish(tw + W_ILAST, kIncl | inc.last);
+            s_pref[0] = pre.rec;
+            s_pref[1] = pre.fld;
+            s_pref[2] = pre.col;
+            s_pref[3] = pre.last;
+        }
     }
     __syncthreads();
 
     const int64_t R0 = (int64_t)s_pref[0];
     const int64_t F0 = (int64_t)s_pref[1];
-    const int64_t C0 = (int64_t)(s_pref[2] & kColVal);
-    const unsigned long long lastw = s_pref[3];
-    Cnt tagg = {0u, 0u, 0u};
-    for (int w = 0; w < NW; ++w) tagg = cnt_combine(tagg, s_wcnt[w]);
+    const int64_t C0 = (int64_t)(s_pref[2] & kColVal);  // always absolute: seeded with (abs, 0)
+    const u64 lastw = s_pref[3];
     const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
-
-    // ---- 6. emit structure ------------------------------------------------------------------
-    {
-        uint32_t L = cex.nf, lr = cex.nr;
-        int64_t col = (cex.col & kCAbs) ? (int64_t)(cex.col & ~kCAbs) : C0 + (int64_t)cex.col;
-        uint32_t m = dmask;
-        while (m) {
-            const int i = __ffs(m) - 1;
-            m &= m - 1;
-            s_pos[L] = (uint16_t)(c0 + i);
-            if (F0 + L < p.cap_fields) p.column_ids[F0 + L] = (int32_t)col;
-            if ((rmask >> i) & 1u) { s_recend[lr++] = (uint16_t)L; col = 0; }
-            else ++col;
-            ++L;
-        }
-        if (vend) {
-            s_pos[L] = (uint16_t)tile_len;
-            if (F0 + L < p.cap_fields) p.column_ids[F0 + L] = (int32_t)col;
-            s_recend[lr++] = (uint16_t)L;
-        }
-    }
-    __syncthreads();
-    for (int k = tid; k < Ft; k += NT) {
-        const int64_t f = F0 + 1 + k;
-        if (f <= p.cap_fields) p.field_offsets[f] = tile_start + s_pos[k] + 1;
-    }
-    for (int k = tid; k < Rt; k += NT) {
-        const int64_t r = R0 + 1 + k;
-        if (r <= p.cap_records) p.record_offsets[r] = F0 + s_recend[k] + 1;
-    }
-
-    // ---- 7. typed columns, column-major over (column, local record) ------------------------
     const int ncols = p.ncols;
-    const int nrec = Rt + 1;  // records closed here plus the open one
-    const int items = nrec * ncols;
-    const float rcp = 1.0f / (float)nrec;
     const ByteSrc src{s_bytes, p.in, tile_start};
     const bool last_has = (lastw & kLastHas) != 0;
     const int64_t last_pos = (int64_t)(lastw & kLastPos);
     const uint32_t last_sa = (uint32_t)((lastw >> 56) & 0xf);
     const bool prev_ctl = (lastw & kLastCtl) != 0;
+
+    // control bit of byte b (b may precede the tile only for the tile's first field)
+    auto ctl_at_begin = [&](int64_t b) -> bool {
+        if (b >= tile_start) {
+            const int r = (int)(b - tile_start);
+            return (s_ctl[r >> 5] >> (r & 31)) & 1u;
+        }
+        const uint32_t by = p.in[b];
+        uint32_t x;
+        if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (last_sa >> 2)], (last_sa & 3) * 8, 8);
+        else x = __builtin_amdgcn_ubfe(s_tcomb[by], last_sa * 8, 8);
+        return (x >> 6) == kTagControl;
+    };
+    auto ctl_at_end = [&](int64_t e) -> bool {  // control bit of byte e-1
+        if (e - 1 >= tile_start) {
+            const int r = (int)(e - 1 - tile_start);
+            return (s_ctl[r >> 5] >> (r & 31)) & 1u;
+        }
+        return prev_ctl;
+    };
+
     int64_t nerr = 0, nragged = 0;
-    for (int q = tid; q < items; q += NT) {
-        int c = (int)((float)q * rcp);
-        if (c * nrec > q) --c;
-        else if ((c + 1) * nrec <= q) ++c;
-        const int lr = q - c * nrec;
-        const int first = lr == 0 ? 0 : s_recend[lr - 1] + 1;
-        const int64_t cf = lr == 0 ? C0 : 0;
-        const int last = lr < Rt ? (int)s_recend[lr] : Ft - 1;
-        const int64_t rec = R0 + lr;
-        if (c == 0 && lr < Rt && cf + (last - first + 1) != ncols) ++nragged;
-        if (c < cf) continue;
-        const int64_t Lz = first + (c - cf);
-        const int ty = s_types[c];
-        if (ty == PP_SKIP) continue;
-        ColDesc cd = p.cols[c];
-        if (Lz > last) {
-            if (lr < Rt && rec < p.cap_records) {  // missing column of a short record
-                ((int64_t*)cd.values)[rec] = 0;  // 0 and 0.0 share the bit pattern
-                cd.valid[rec] = 0;
-                if (ty == PP_STRING) cd.str_end[rec] = 0;
+    if (Ft <= FCAP && Rt <= RCAP) {
+        // ---- 6. emit structure through LDS --------------------------------------------------
+        {
+            uint32_t L = cex.nf, lr = cex.nr;
+            int64_t col = (cex.col & kCAbs) ? (int64_t)(cex.col & ~kCAbs) : C0 + (int64_t)cex.col;
+            M m = dmask;
+            while (m) {
+                const int i = B > 32 ? __ffsll((long long)m) - 1 : __ffs((int)m) - 1;
+                m &= m - 1;
+                s_pos[L] = (uint16_t)(c0 + i);
+                if (F0 + L < p.cap_fields) p.column_ids[F0 + L] = (int32_t)col;
+                if ((rmask >> i) & 1u) { s_recend[lr++] = (uint16_t)L; col = 0; }
+                else ++col;
+                ++L;
             }
-            continue;
+            if (vend) {
+                s_pos[L] = (uint16_t)tile_len;
+                if (F0 + L < p.cap_fields) p.column_ids[F0 + L] = (int32_t)col;
+                s_recend[lr] = (uint16_t)L;
+            }
         }
-        const int L = (int)Lz;
-        const int64_t e = tile_start + s_pos[L];
-        const int64_t b = L == 0 ? (last_has ? last_pos + 1 : 0) : tile_start + s_pos[L - 1] + 1;
-        // strip one leading and one trailing control symbol (enclosing quotes)
-        int64_t begin = b, end = e;
-        if (end > begin) {
-            bool ctl;
-            if (b >= tile_start) {
-                const int r = (int)(b - tile_start);
-                ctl = (s_ctl[r >> 5] >> (r & 31)) & 1u;
+        __syncthreads();
+        for (int k = tid; k < Ft; k += NT) {
+            const int64_t f = F0 + 1 + k;
+            if (f <= p.cap_fields) p.field_offsets[f] = tile_start + s_pos[k] + 1;
+        }
+        for (int k = tid; k < Rt; k += NT) {
+            const int64_t r = R0 + 1 + k;
+            if (r <= p.cap_records) p.record_offsets[r] = F0 + s_recend[k] + 1;
+        }
+
+        // ---- 7. typed columns, column-major over (column, local record) ------------------
+        const int nrec = Rt + 1;  // records closed here plus the open one
+        const int items = nrec * ncols;
+        const float rcp = 1.0f / (float)nrec;
+        for (int q = tid; q < items; q += NT) {
+            int c = (int)((float)q * rcp);
+            if (c * nrec > q) --c;
+            else if ((c + 1) * nrec <= q) ++c;
+            const int lr = q - c * nrec;
+            const int first = lr == 0 ? 0 : s_recend[lr - 1] + 1;
+            const int64_t cf = lr == 0 ? C0 : 0;
+            const int last = lr < Rt ? (int)s_recend[lr] : Ft - 1;
+            const int64_t rec = R0 + lr;
+            if (c == 0 && lr < Rt && cf + (last - first + 1) != ncols) ++nragged;
+            if (c < cf) continue;
+            const int ty = s_types[c];
+            if (ty == PP_SKIP) continue;
+            const int64_t Lz = first + (c - cf);
+            if (Lz > last) {
+                if (lr < Rt) store_missing(p, c, ty, rec);  // missing column of a short record
+                continue;
+            }
+            const int L = (int)Lz;
+            const int64_t e = tile_start + s_pos[L];
+            const int64_t b = L == 0 ? (last_has ? last_pos + 1 : 0) : tile_start + s_pos[L - 1] + 1;
+            const bool cfst = e > b && ctl_at_begin(b);
+            const bool clst = e > b && ctl_at_end(e);
+            nerr += store_field(p, src, c, ty, rec, b, e, cfst, clst);
+        }
+        if (ncols == 0 && tid == 0) nragged = Rt;
+    } else {
+        // ---- 6'/7'. per-thread path: each thread closes the fields whose delimiter it holds
+        uint32_t L = cex.nf;
+        int64_t lr = cex.nr;
+        int64_t col = (cex.col & kCAbs) ? (int64_t)(cex.col & ~kCAbs) : C0 + (int64_t)cex.col;
+        int64_t prev = cex.last ? tile_start + (int64_t)cex.last - 1 : (last_has ? last_pos : -1);
+        M m = dmask;
+        const int cnt = (int)popc(dmask) + (int)vend;
+        for (int k = 0; k < cnt; ++k) {
+            int64_t pos;
+            bool isrec;
+            if (m) {
+                const int i = B > 32 ? __ffsll((long long)m) - 1 : __ffs((int)m) - 1;
+                m &= m - 1;
+                pos = cstart + i;
+                isrec = (rmask >> i) & 1u;
+            } else {  // the virtual delimiter at the end of input
+                pos = n;
+                isrec = true;
+            }
+            const int64_t f = F0 + L;
+            if (f + 1 <= p.cap_fields) p.field_offsets[f + 1] = pos + 1;
+            if (f < p.cap_fields) p.column_ids[f] = (int32_t)col;
+            const int64_t rec = R0 + lr;
+            if (col < ncols) {
+                const int ty = s_types[col];
+                if (ty != PP_SKIP) {
+                    const int64_t b = prev + 1;
+                    const bool cfst = pos > b && ctl_at_begin(b);
+                    const bool clst = pos > b && ctl_at_end(pos);
+                    nerr += store_field(p, src, (int)col, ty, rec, b, pos, cfst, clst);
+                }
+            }
+            if (isrec) {
+                if (col + 1 != ncols) ++nragged;
+                for (int64_t c = col + 1; c < ncols; ++c) store_missing(p, (int)c, s_types[c], rec);
+                if (rec + 1 <= p.cap_records) p.record_offsets[rec + 1] = f + 1;
+                ++lr;
+                col = 0;
             } else {
-                uint32_t x;
-                const uint32_t by = p.in[b];
-                if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (last_sa >> 2)], (last_sa & 3) * 8, 8);
-                else x = __builtin_amdgcn_ubfe(s_tcomb[by], last_sa * 8, 8);
-                ctl = (x >> 6) == (uint32_t)kTagControl;
+                ++col;
             }
-            if (ctl) ++begin;
-        }
-        if (end - 1 >= begin) {
-            bool ctl;
-            if (e - 1 >= tile_start) {
-                const int r = (int)(e - 1 - tile_start);
-                ctl = (s_ctl[r >> 5] >> (r & 31)) & 1u;
-            } else {
-                ctl = prev_ctl;
-            }
-            if (ctl) --end;
-        }
-        if (rec >= p.cap_records) {
-            // still count conversion errors so the result does not depend on capacity
-            if (ty != PP_STRING && end > begin) {
-                bool ok;
-                int64_t iv;
-                double dv;
-                if (ty == PP_INT64) ok = conv_int64(src, begin, end, &iv);
-                else if (ty == PP_FLOAT64) ok = conv_float64(src, begin, end, &dv);
-                else if (ty == PP_TIMESTAMP_S) ok = conv_timestamp(src, begin, end, &iv);
-                else ok = conv_date(src, begin, end, &iv);
-                nerr += !ok;
-            }
-            continue;
-        }
-        if (ty == PP_STRING) {
-            ((int64_t*)cd.values)[rec] = begin;
-            cd.str_end[rec] = end;
-            cd.valid[rec] = 1;
-        } else if (end == begin) {
-            ((int64_t*)cd.values)[rec] = 0;
-            cd.valid[rec] = 0;
-        } else if (ty == PP_FLOAT64) {
-            double dv = 0.0;
-            const bool ok = conv_float64(src, begin, end, &dv);
-            ((double*)cd.values)[rec] = ok ? dv : 0.0;
-            cd.valid[rec] = ok;
-            nerr += !ok;
-        } else {
-            int64_t iv = 0;
-            bool ok;
-            if (ty == PP_INT64) ok = conv_int64(src, begin, end, &iv);
-            else if (ty == PP_TIMESTAMP_S) ok = conv_timestamp(src, begin, end, &iv);
-            else ok = conv_date(src, begin, end, &iv);
-            ((int64_t*)cd.values)[rec] = ok ? iv : 0;
-            cd.valid[rec] = ok;
-            nerr += !ok;
+            prev = pos;
+            ++L;
         }
     }
-    if (ncols == 0 && tid == 0) nragged = Rt;
+
     nerr = wave_sum(nerr);
     nragged = wave_sum(nragged);
     if (lane == 0 && (nerr | nragged)) {
-        atomicAdd(&s_err, (unsigned long long)nerr);
-        atomicAdd(&s_ragged, (unsigned long long)nragged);
+        atomicAdd(&s_err, (u64)nerr);
+        atomicAdd(&s_ragged, (u64)nragged);
     }
     __syncthreads();
     if (tid == 0) {
-        if (s_err) atomicAdd((unsigned long long*)&p.result->num_conversion_errors, s_err);
-        if (s_ragged) atomicAdd((unsigned long long*)&p.result->num_ragged_records, s_ragged);
+        if (s_err) atomicAdd((u64*)&p.result->num_conversion_errors, s_err);
+        if (s_ragged) atomicAdd((u64*)&p.result->num_ragged_records, s_ragged);
         if (tile == (uint32_t)p.num_tiles - 1) {
             const int64_t R = R0 + Rt, F = F0 + Ft;
             const uint32_t fin = s_final;
@@ -685,22 +870,20 @@ __global__ void parse_init(Params p, size_t nwords)
 
 // ---- host side ------------------------------------------------------------------------
 
-constexpr int kDefaultNT = 256;
-constexpr int kDefaultB = 32;
+struct Shape {
+    int nt, b;
+};
+constexpr Shape kShapes[] = {{512, 64}, {256, 64}, {256, 32}, {512, 32}, {256, 16}};
+constexpr Shape kDefaultShape = {512, 64};
 
-static int tile_bytes(const pp_options_t* o)
+static bool shape_of(const pp_options_t* o, Shape* s)
 {
-    int nt = (o && o->block_threads) ? o->block_threads : kDefaultNT;
-    int b = (o && o->bytes_per_thread) ? o->bytes_per_thread : kDefaultB;
-    return nt * b;
-}
-
-static bool options_ok(const pp_options_t* o)
-{
-    if (!o) return true;
-    int nt = o->block_threads ? o->block_threads : kDefaultNT;
-    int b = o->bytes_per_thread ? o->bytes_per_thread : kDefaultB;
-    return nt == 256 && (b == 16 || b == 32);
+    Shape r = kDefaultShape;
+    if (o && o->block_threads) r.nt = o->block_threads;
+    if (o && o->bytes_per_thread) r.b = o->bytes_per_thread;
+    for (const Shape& k : kShapes)
+        if (k.nt == r.nt && k.b == r.b) { *s = r; return true; }
+    return false;
 }
 
 static pp_status_t check_dfa(const pp_dfa_t* d)
@@ -720,16 +903,24 @@ static pp_status_t check_dfa(const pp_dfa_t* d)
     return PP_OK;
 }
 
+template <int NT, int B>
+static void launch_tiles(const Params& p, bool ns8, int64_t tiles, hipStream_t s)
+{
+    if (ns8) hipLaunchKernelGGL((parse_tiles<NT, B, true>), dim3((unsigned)tiles), dim3(NT), 0, s, p);
+    else hipLaunchKernelGGL((parse_tiles<NT, B, false>), dim3((unsigned)tiles), dim3(NT), 0, s, p);
+}
+
 }  // namespace pp
 
 using namespace pp;
 
 extern "C" size_t pp_workspace_size(int64_t n, const pp_options_t* opts)
 {
-    if (n < 0 || !options_ok(opts)) return 0;
-    const int64_t tb = tile_bytes(opts);
+    Shape sh;
+    if (n < 0 || !shape_of(opts, &sh)) return 0;
+    const int64_t tb = (int64_t)sh.nt * sh.b;
     const int64_t tiles = (n + tb - 1) / tb;
-    return 256 + (size_t)tiles * kWordsPerTile * sizeof(unsigned long long);
+    return 256 + (size_t)tiles * kWordsPerTile * sizeof(u64);
 }
 
 extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
@@ -737,7 +928,8 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
                                 size_t ws_bytes, const pp_options_t* opts, void* stream)
 {
     if (n < 0 || (n > 0 && !d_in) || !schema || !out || !d_ws || !out->d_result) return PP_ERR_ARG;
-    if (!options_ok(opts)) return PP_ERR_ARG;
+    Shape sh;
+    if (!shape_of(opts, &sh)) return PP_ERR_ARG;
     if (out->cap_records < 0 || out->cap_fields < 0) return PP_ERR_ARG;
     if (!out->d_record_offsets || !out->d_field_offsets) return PP_ERR_ARG;
     if (out->cap_fields > 0 && !out->d_column_ids) return PP_ERR_ARG;
@@ -759,8 +951,8 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     p.column_ids = out->d_column_ids;
     p.result = out->d_result;
     p.counter = (unsigned int*)d_ws;
-    p.words = (unsigned long long*)((char*)d_ws + 256);
-    const int tb = tile_bytes(opts);
+    p.words = (u64*)((char*)d_ws + 256);
+    const int64_t tb = (int64_t)sh.nt * sh.b;
     const int64_t tiles = (n + tb - 1) / tb;
     if (tiles > 0x7fffffff) return PP_ERR_UNSUPPORTED;
     p.num_tiles = (int32_t)tiles;
@@ -795,15 +987,12 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     hipLaunchKernelGGL(parse_init, dim3(init_blocks), dim3(256), 0, s, p, nwords);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
     if (tiles == 0) return PP_OK;
-    const int b = (opts && opts->bytes_per_thread) ? opts->bytes_per_thread : kDefaultB;
     const bool ns8 = dfa->num_states > 4;
-    if (b == 32) {
-        if (ns8) hipLaunchKernelGGL((parse_tiles<256, 32, true>), dim3((unsigned)tiles), dim3(256), 0, s, p);
-        else hipLaunchKernelGGL((parse_tiles<256, 32, false>), dim3((unsigned)tiles), dim3(256), 0, s, p);
-    } else {
-        if (ns8) hipLaunchKernelGGL((parse_tiles<256, 16, true>), dim3((unsigned)tiles), dim3(256), 0, s, p);
-        else hipLaunchKernelGGL((parse_tiles<256, 16, false>), dim3((unsigned)tiles), dim3(256), 0, s, p);
-    }
+    if (sh.nt == 512 && sh.b == 64) launch_tiles<512, 64>(p, ns8, tiles, s);
+    else if (sh.nt == 256 && sh.b == 64) launch_tiles<256, 64>(p, ns8, tiles, s);
+    else if (sh.nt == 256 && sh.b == 32) launch_tiles<256, 32>(p, ns8, tiles, s);
+    else if (sh.nt == 512 && sh.b == 32) launch_tiles<512, 32>(p, ns8, tiles, s);
+    else launch_tiles<256, 16>(p, ns8, tiles, s);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
     return PP_OK;
 }

@@ -38,9 +38,10 @@ def test_no_oracle_in_product_library():
 
 def test_workspace_size_and_status_text():
     assert pp.workspace_size(0) == 256
-    assert pp.workspace_size(8192) == 256 + 5 * 8
-    assert pp.workspace_size(8193) == 256 + 2 * 5 * 8
-    assert pp.workspace_size(1 << 20, pp.options(16, 256)) == 256 + 256 * 5 * 8
+    assert pp.workspace_size(32768) == 256 + 8 * 8          # default: 512 threads x 64 B
+    assert pp.workspace_size(32769) == 256 + 2 * 8 * 8
+    assert pp.workspace_size(1 << 20, pp.options(16, 256)) == 256 + 256 * 8 * 8
+    assert pp.workspace_size(1 << 20, pp.options(48, 256)) == 0
     assert pp.lib().pp_status_str(0) == b"ok"
     assert pp.lib().pp_status_str(-2) == b"invalid DFA"
 
@@ -78,3 +79,4 @@ def test_argument_errors_are_synchronous():
     assert _call(good, in_ptr=None) == -1
     assert _call(good, opts=pp.options(48, 256)) == -1
     assert _call(good, opts=pp.options(32, 128)) == -1
+    assert _call(good, opts=pp.options(64, 1024)) == -1

@@ -1,10 +1,11 @@
 """GPU parity: the HIP path through the C ABI against the oracle, bit-exact.
 
-Sizes span several 8 KiB tiles (and 4 KiB tiles for the 16-byte chunk
-option) with ragged tails; the edge cases cover empty input, inputs ending
-at and off tile boundaries, fields and quotes spanning tiles, a tile of
-nothing but delimiters, invalid input, unterminated quotes, capacity, an
-unaligned input pointer, 3- to 8-state DFAs, and hard float conversions.
+Sizes span several tiles (32 KiB by default; 4-16 KiB for the other launch
+shapes) with ragged tails; the edge cases cover empty input, inputs ending
+at and off tile boundaries, fields and quotes spanning tiles, tiles of
+nothing but delimiters or tiny records (the per-thread fallback path),
+invalid input, unterminated quotes, capacity, an unaligned input pointer,
+3- to 8-state DFAs, and hard float conversions.
 """
 import random
 
@@ -20,7 +21,13 @@ torch = pytest.importorskip("torch")
 pytestmark = [pytest.mark.gpu,
               pytest.mark.skipif(not torch.cuda.is_available(), reason="needs a GPU")]
 
-TILE = 8192
+TILE = 32768  # default launch shape: 512 threads x 64 bytes
+SHAPES = [None, (64, 256), (32, 256), (32, 512), (16, 256)]  # (bytes/thread, threads)
+SHAPE_IDS = ["512x64", "256x64", "256x32", "512x32", "256x16"]
+
+
+def opts_of(shape):
+    return pp.options(*shape) if shape else None
 
 
 def u8(b):
@@ -47,20 +54,41 @@ def test_tiny_inputs(text):
         assert_same(u8(text), dfa, [D.STRING, D.INT64, D.STRING])
 
 
-@pytest.mark.parametrize("n", [TILE - 1, TILE, TILE + 1, 2 * TILE, 3 * TILE + 17])
-def test_tile_boundaries(n):
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_tile_boundaries(shape):
+    tile = (shape[0] * shape[1]) if shape else TILE
     g = datagen.c1()
-    data = g.data[:n].copy()
-    assert_same(data, D.csv4(), D.SCHEMA_C1.types)
-    # the same length ending in a record delimiter exactly at the boundary
-    data[-1] = ord("\n")
-    assert_same(data, D.csv4(), D.SCHEMA_C1.types)
+    for n in (tile - 1, tile, tile + 1, 2 * tile, 3 * tile + 17):
+        data = g.data[:n].copy()
+        assert_same(data, D.csv4(), D.SCHEMA_C1.types, opts=opts_of(shape))
+        # the same length ending in a record delimiter exactly at the boundary
+        data[-1] = ord("\n")
+        assert_same(data, D.csv4(), D.SCHEMA_C1.types, opts=opts_of(shape))
 
 
-def test_all_delimiters():
-    """Every byte a delimiter: the per-tile staging at its maximum."""
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_all_delimiters(shape):
+    """Every byte a delimiter: more fields (and records) per tile than the
+    LDS staging holds, so every tile takes the per-thread path."""
     for ch in (b",", b"\n"):
-        assert_same(u8(ch * (3 * TILE + 5)), D.csv4(), [D.INT64, D.STRING, D.FLOAT64])
+        assert_same(u8(ch * (3 * TILE + 5)), D.csv4(), [D.INT64, D.STRING, D.FLOAT64], opts=opts_of(shape))
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_tiny_records_fallback_and_mixed_tiles(shape):
+    """Records of 2-12 bytes exceed the per-tile record staging; longer ones
+    in between keep some tiles on the staged path."""
+    rnd = random.Random(11)
+    c1 = bytes(datagen.c1().data[:20000])
+    parts = []
+    while sum(map(len, parts)) < 4 * TILE:
+        if rnd.random() < 0.5:
+            parts.append(b"1,2\n" * rnd.randint(1, 4000))
+        else:
+            parts.append(c1[:rnd.randint(1, 20000)])
+    data = b"".join(parts)
+    assert_same(u8(data), D.csv4(), D.SCHEMA_C1.types, opts=opts_of(shape))
+    assert_same(u8(data), D.csv4(), [D.INT64, D.INT64], opts=opts_of(shape))
 
 
 def test_long_quoted_field_spanning_tiles():
@@ -97,9 +125,11 @@ def test_unaligned_input():
         assert_same(g.data[:4 * TILE + 77], D.csv4(), D.SCHEMA_C1.types, offset=off)
 
 
-def test_chunk16_option():
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_launch_shapes_c1(shape):
     g = datagen.c1()
-    assert_same(g.data[:200000], D.csv4(), D.SCHEMA_C1.types, opts=pp.options(16, 256))
+    assert_same(g.data, D.csv4(), D.SCHEMA_C1.types, opts=opts_of(shape))
+    assert_same(g.data, D.paper6(), D.SCHEMA_C1.types, opts=opts_of(shape))
 
 
 def test_ragged_and_extra_fields():
@@ -119,11 +149,12 @@ def test_ragged_and_extra_fields():
 def test_random_symbol_soup(name):
     dfa = D.ALL_DFAS[name]()
     alphabet = b"".join(dfa.group_symbols) + b"a1.-"
-    rnd = random.Random(hash(name) & 0xffff)
+    rnd = random.Random(sum(name.encode()))
     types = [D.STRING, D.INT64, D.FLOAT64, D.STRING, D.INT64]
     for n in (100, 5000, 3 * TILE + 11):
         data = bytes(rnd.choice(alphabet) for _ in range(n))
-        assert_same(u8(data), dfa, types)
+        for shape in (None, (16, 256)):
+            assert_same(u8(data), dfa, types, opts=opts_of(shape))
 
 
 # ---- workloads ------------------------------------------------------------------------------
@@ -134,9 +165,10 @@ def test_c1_full():
     assert_same(g.data, D.paper6(), D.SCHEMA_C1.types)
 
 
-def test_c2_c3_slices():
-    assert_same(datagen.c2(nbytes=24 << 20).data, D.csv4(), D.SCHEMA_C2.types)
-    assert_same(datagen.c3(nbytes=40 << 20).data, D.csv4(), D.SCHEMA_C3.types)
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_c2_c3_slices(shape):
+    assert_same(datagen.c2(nbytes=24 << 20).data, D.csv4(), D.SCHEMA_C2.types, opts=opts_of(shape))
+    assert_same(datagen.c3(nbytes=40 << 20).data, D.csv4(), D.SCHEMA_C3.types, opts=opts_of(shape))
 
 
 @pytest.mark.parametrize("name,delim,qstyle", [("csv4", b"\t", 1), ("s5", b"|", 1), ("s3", b",", 3),
