@@ -114,10 +114,16 @@ __device__ inline bool conv_timestamp(const Src& src, int64_t b, int64_t e, int6
 
 __device__ inline double exact_pow10(int k)
 {
-    // 10^0 .. 10^22 are exactly representable in binary64.
-    const double t[23] = {1e0,  1e1,  1e2,  1e3,  1e4,  1e5,  1e6,  1e7,  1e8,  1e9,  1e10, 1e11,
-                          1e12, 1e13, 1e14, 1e15, 1e16, 1e17, 1e18, 1e19, 1e20, 1e21, 1e22};
-    return t[k];
+    // 10^k for 0 <= k <= 22 by binary exponentiation. Every partial product
+    // is some 10^j with j <= 22, exactly representable in binary64, so each
+    // multiplication is exact and no table in memory is needed.
+    double r = 1.0;
+    if (k & 1) r *= 1e1;
+    if (k & 2) r *= 1e2;
+    if (k & 4) r *= 1e4;
+    if (k & 8) r *= 1e8;
+    if (k & 16) r *= 1e16;
+    return r;
 }
 
 constexpr int kDecCap = 800;

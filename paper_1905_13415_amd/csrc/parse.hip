@@ -18,8 +18,8 @@
 //   5. record counts (+), field counts (+), column carries (the abs/rel
 //      operator of Sec. 3.2) and the last delimiter position, scanned the
 //      same way;
-//   6. delimiter positions staged in LDS and written coalesced as field and
-//      record offsets; column ids written per delimiter;
+//   6. delimiter positions, column ids and record ends staged in LDS, then
+//      written coalesced as field offsets, column ids and record offsets;
 //   7. typed conversion (Sec. 3.3): the tile's (column, record) pairs are
 //      visited column-major, so a wavefront converts one column's type and
 //      its stores into that typed column are contiguous. This takes the place
@@ -36,6 +36,7 @@
 #include <type_traits>
 
 #include "convert.h"
+#include "convert_fast.h"
 #include "parparaw.h"
 
 namespace pp {
@@ -61,6 +62,7 @@ struct Params {
     pp_result_t* result;
     u64* words;             // kWordsPerTile per tile
     unsigned int* counter;  // tile ticket
+    uint32_t* tables;       // 2 x 512 dwords: byte -> next states, byte -> (next*8 | tag<<6) per state
     int32_t num_tiles;
     int32_t ncols;
     int32_t num_states;
@@ -81,6 +83,8 @@ struct Params {
 // words: an aggregate is never overwritten, so a reader always finds either
 // all four inclusive words or both aggregate words of a tile.
 constexpr int kWordsPerTile = 8;
+// workspace: [ticket counter | pad] [byte tables, 4 KiB] [kWordsPerTile words per tile]
+constexpr size_t kWsHeader = 256, kWsTables = 4096;
 enum { W_STATE = 0, W_AGG0 = 1, W_AGG1 = 2, W_IREC = 3, W_IFLD = 4, W_ICOL = 5, W_ILAST = 6 };
 constexpr u64 kAgg = 1ull << 62, kIncl = 2ull << 62;
 constexpr u64 kPayload = (1ull << 62) - 1;
@@ -192,6 +196,16 @@ __device__ inline SV<NS8> shfl_down_sv(SV<NS8> v, int d)
     return r;
 }
 
+// One DFA step through the combined table: state*8 -> next state*8.
+template <bool NS8>
+__device__ inline uint32_t step_state(const uint32_t* tcomb, uint32_t b, uint32_t s8)
+{
+    uint32_t x;
+    if constexpr (NS8) x = __builtin_amdgcn_ubfe(tcomb[2 * b + (s8 >> 5)], s8 & 31u, 8);
+    else x = __builtin_amdgcn_ubfe(tcomb[b], s8, 8);
+    return x & 0x38u;
+}
+
 // ---- count scan element within a tile (Sec. 3.2) ---------------------------------
 // nr: record delimiters; nf: delimiters (fields closed); col: column carry,
 // bit 31 = abs; last: tile-relative position + 1 of the last delimiter (0: none).
@@ -259,6 +273,7 @@ struct ByteSrc {
     const uint8_t* lds;
     const uint8_t* g;
     int64_t tile_start;
+    int tile_size;  // bytes of the LDS tile buffer (a multiple of 4)
     __device__ uint32_t operator()(int64_t pos) const
     {
         int64_t r = pos - tile_start;
@@ -275,14 +290,14 @@ __device__ inline int64_t wave_sum(int64_t v)
 // Strip the enclosing control symbols of field [b, e) and convert it into
 // column c, record rec. ctl_first/ctl_last_sym: whether bytes b and e-1 are
 // control symbols. Returns 1 on a conversion error.
-__device__ inline int store_field(const Params& p, const ByteSrc& src, int c, int ty, int64_t rec,
-                                  int64_t b, int64_t e, bool ctl_first, bool ctl_last_sym)
+__device__ inline int store_field(const Params& p, const ColDesc* cols, const ByteSrc& src, int c, int ty,
+                                  int64_t rec, int64_t b, int64_t e, bool ctl_first, bool ctl_last_sym)
 {
     int64_t begin = b, end = e;
     if (end > begin && ctl_first) ++begin;
     if (end - 1 >= begin && ctl_last_sym) --end;
     const bool store = rec < p.cap_records;
-    const ColDesc cd = p.cols[c];
+    const ColDesc cd = cols[c];
     if (ty == PP_STRING) {
         if (store) {
             ((int64_t*)cd.values)[rec] = begin;
@@ -300,7 +315,27 @@ __device__ inline int store_field(const Params& p, const ByteSrc& src, int c, in
     }
     bool ok;
     u64 bits;
-    if (ty == PP_FLOAT64) {
+    int r = -1;
+    const int64_t off = begin - src.tile_start;
+    const int len = (int)(end - begin);
+    if (off >= 0 && len <= kWin) {  // short field inside the tile: parse from registers
+        const Win x = load_win(reinterpret_cast<const uint32_t*>(src.lds), src.tile_size, (int)off);
+        if (ty == PP_FLOAT64) {
+            double dv = 0.0;
+            r = win_float64(x, len, &dv);
+            bits = __builtin_bit_cast(u64, dv);
+        } else {
+            int64_t iv = 0;
+            if (ty == PP_INT64) r = win_int64(x, len, &iv);
+            else if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
+            else r = win_date(x, len, &iv);
+            bits = (u64)iv;
+        }
+    }
+    if (r >= 0) {
+        ok = r == 1;
+        if (!ok) bits = 0ull;
+    } else if (ty == PP_FLOAT64) {
         double dv = 0.0;
         ok = conv_float64(src, begin, end, &dv);
         bits = ok ? __builtin_bit_cast(u64, dv) : 0ull;
@@ -318,10 +353,10 @@ __device__ inline int store_field(const Params& p, const ByteSrc& src, int c, in
     return !ok;
 }
 
-__device__ inline void store_missing(const Params& p, int c, int ty, int64_t rec)
+__device__ inline void store_missing(const Params& p, const ColDesc* cols, int c, int ty, int64_t rec)
 {
     if (rec >= p.cap_records || ty == PP_SKIP) return;
-    const ColDesc cd = p.cols[c];
+    const ColDesc cd = cols[c];
     ((u64*)cd.values)[rec] = 0;  // 0 and 0.0 share the bit pattern
     cd.valid[rec] = 0;
     if (ty == PP_STRING) cd.str_end[rec] = 0;
@@ -335,7 +370,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     using M = std::conditional_t<(B > 32), u64, uint32_t>;
     constexpr int TILE = NT * B;
     constexpr int NW = NT / 64;
-    constexpr int FCAP = TILE / 2;   // delimiters staged per tile
+    constexpr int FCAP = TILE / 4;   // delimiters staged per tile
     constexpr int RCAP = TILE / 16;  // records staged per tile
     static_assert(TILE <= 32768, "u16 positions");
 
@@ -343,9 +378,11 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     __shared__ uint32_t s_tcomb[NS8 ? 512 : 256];  // byte -> per state (next*8 | tag<<6)
     __shared__ __align__(16) uint8_t s_bytes[TILE];
     __shared__ uint16_t s_pos[FCAP];     // tile-relative delimiter positions
+    __shared__ uint16_t s_colid[FCAP];   // column of the field each delimiter closes
     __shared__ uint16_t s_recend[RCAP];  // local field index of each record delimiter
     __shared__ uint32_t s_ctl[TILE / 32];  // control-symbol bitmap of the tile
     __shared__ uint8_t s_types[PP_MAX_COLUMNS];
+    __shared__ ColDesc s_cols[PP_MAX_COLUMNS];
     __shared__ SV<NS8> s_wsv[NW];
     __shared__ Cnt s_wcnt[NW];
     __shared__ uint32_t s_tile, s_s0, s_final, s_last_sa, s_ctl_last;
@@ -363,27 +400,15 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         s_err = 0;
         s_ragged = 0;
     }
-    // per-byte transition rows from the DFA's group table (Table 1 layout)
-    for (int b = tid; b < 256; b += NT) {
-        const uint32_t g = p.group_of[b];
-        uint32_t lo = 0, hi = 0, clo = 0, chi = 0;
-        for (int s = 0; s < (NS8 ? 8 : 4); ++s) {
-            const bool real = s < p.num_states;
-            const uint32_t nx = real ? p.next[g][s] : (uint32_t)s;
-            const uint32_t tg = real ? p.tag[g][s] : 0u;
-            const uint32_t cb = (nx * 8u) | (tg << 6);
-            if (s < 4) { lo |= nx << (8 * s); clo |= cb << (8 * s); }
-            else { hi |= nx << (8 * (s - 4)); chi |= cb << (8 * (s - 4)); }
-        }
-        if constexpr (NS8) {
-            s_tnext[2 * b] = lo; s_tnext[2 * b + 1] = hi;
-            s_tcomb[2 * b] = clo; s_tcomb[2 * b + 1] = chi;
-        } else {
-            s_tnext[b] = lo;
-            s_tcomb[b] = clo;
-        }
+    // per-byte transition rows, precomputed by parse_init from the group table
+    for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
+        s_tnext[k] = p.tables[k];
+        s_tcomb[k] = p.tables[512 + k];
     }
-    for (int c = tid; c < p.ncols; c += NT) s_types[c] = p.types[c];
+    for (int c = tid; c < p.ncols; c += NT) {
+        s_types[c] = p.types[c];
+        s_cols[c] = p.cols[c];
+    }
     __syncthreads();
 
     const uint32_t tile = s_tile;
@@ -532,15 +557,17 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 
     // first transition into the (absorbing) invalid state
     if (p.invalid_state >= 0 && s_start != (uint32_t)p.invalid_state && s_end == (uint32_t)p.invalid_state) {
-        uint32_t s = s_start;
-        for (int i = 0; i < len; ++i) {
-            const uint32_t nx = p.next[p.group_of[s_bytes[c0 + i]]][s];
-            if (nx == (uint32_t)p.invalid_state) {
-                p.result->first_invalid_offset = cstart + i;
-                break;
+        const uint32_t inv8 = (uint32_t)p.invalid_state * 8u;
+        uint32_t r8 = s_start * 8u;
+        int at = -1;
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            if (i < len && at < 0) {
+                r8 = step_state<NS8>(s_tcomb, byte_at(i), r8);
+                if (r8 == inv8) at = i;
             }
-            s = nx;
         }
+        p.result->first_invalid_offset = cstart + at;
     }
 
     auto popc = [](M m) -> uint32_t {
@@ -599,9 +626,11 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         uint32_t sa = 0;
         if (!vend) {
             const int hb = msb(dmask);
-            uint32_t s = s_start;
-            for (int i = 0; i <= hb; ++i) s = p.next[p.group_of[s_bytes[c0 + i]]][s];
-            sa = s;
+            uint32_t r8 = s_start * 8u;
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                if (i <= hb) r8 = step_state<NS8>(s_tcomb, byte_at(i), r8);
+            sa = r8 >> 3;
         }
         s_last_sa = sa;
     }
@@ -686,7 +715,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     const u64 lastw = s_pref[3];
     const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
     const int ncols = p.ncols;
-    const ByteSrc src{s_bytes, p.in, tile_start};
+    const ByteSrc src{s_bytes, p.in, tile_start, TILE};
     const bool last_has = (lastw & kLastHas) != 0;
     const int64_t last_pos = (int64_t)(lastw & kLastPos);
     const uint32_t last_sa = (uint32_t)((lastw >> 56) & 0xf);
@@ -699,9 +728,10 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
             return (s_ctl[r >> 5] >> (r & 31)) & 1u;
         }
         const uint32_t by = p.in[b];
+        const uint32_t s8 = last_sa * 8u;
         uint32_t x;
-        if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (last_sa >> 2)], (last_sa & 3) * 8, 8);
-        else x = __builtin_amdgcn_ubfe(s_tcomb[by], last_sa * 8, 8);
+        if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (s8 >> 5)], s8 & 31u, 8);
+        else x = __builtin_amdgcn_ubfe(s_tcomb[by], s8, 8);
         return (x >> 6) == kTagControl;
     };
     auto ctl_at_end = [&](int64_t e) -> bool {  // control bit of byte e-1
@@ -713,7 +743,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     };
 
     int64_t nerr = 0, nragged = 0;
-    if (Ft <= FCAP && Rt <= RCAP) {
+    if (Ft <= FCAP && Rt <= RCAP && C0 + Ft < 65536) {
         // ---- 6. emit structure through LDS --------------------------------------------------
         {
             uint32_t L = cex.nf, lr = cex.nr;
@@ -723,14 +753,14 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
                 const int i = B > 32 ? __ffsll((long long)m) - 1 : __ffs((int)m) - 1;
                 m &= m - 1;
                 s_pos[L] = (uint16_t)(c0 + i);
-                if (F0 + L < p.cap_fields) p.column_ids[F0 + L] = (int32_t)col;
+                s_colid[L] = (uint16_t)col;
                 if ((rmask >> i) & 1u) { s_recend[lr++] = (uint16_t)L; col = 0; }
                 else ++col;
                 ++L;
             }
             if (vend) {
                 s_pos[L] = (uint16_t)tile_len;
-                if (F0 + L < p.cap_fields) p.column_ids[F0 + L] = (int32_t)col;
+                s_colid[L] = (uint16_t)col;
                 s_recend[lr] = (uint16_t)L;
             }
         }
@@ -738,6 +768,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         for (int k = tid; k < Ft; k += NT) {
             const int64_t f = F0 + 1 + k;
             if (f <= p.cap_fields) p.field_offsets[f] = tile_start + s_pos[k] + 1;
+            if (f - 1 < p.cap_fields) p.column_ids[f - 1] = s_colid[k];
         }
         for (int k = tid; k < Rt; k += NT) {
             const int64_t r = R0 + 1 + k;
@@ -763,7 +794,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
             if (ty == PP_SKIP) continue;
             const int64_t Lz = first + (c - cf);
             if (Lz > last) {
-                if (lr < Rt) store_missing(p, c, ty, rec);  // missing column of a short record
+                if (lr < Rt) store_missing(p, s_cols, c, ty, rec);  // missing column of a short record
                 continue;
             }
             const int L = (int)Lz;
@@ -771,7 +802,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
             const int64_t b = L == 0 ? (last_has ? last_pos + 1 : 0) : tile_start + s_pos[L - 1] + 1;
             const bool cfst = e > b && ctl_at_begin(b);
             const bool clst = e > b && ctl_at_end(e);
-            nerr += store_field(p, src, c, ty, rec, b, e, cfst, clst);
+            nerr += store_field(p, s_cols, src, c, ty, rec, b, e, cfst, clst);
         }
         if (ncols == 0 && tid == 0) nragged = Rt;
     } else {
@@ -804,12 +835,12 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
                     const int64_t b = prev + 1;
                     const bool cfst = pos > b && ctl_at_begin(b);
                     const bool clst = pos > b && ctl_at_end(pos);
-                    nerr += store_field(p, src, (int)col, ty, rec, b, pos, cfst, clst);
+                    nerr += store_field(p, s_cols, src, (int)col, ty, rec, b, pos, cfst, clst);
                 }
             }
             if (isrec) {
                 if (col + 1 != ncols) ++nragged;
-                for (int64_t c = col + 1; c < ncols; ++c) store_missing(p, (int)c, s_types[c], rec);
+                for (int64_t c = col + 1; c < ncols; ++c) store_missing(p, s_cols, (int)c, s_types[c], rec);
                 if (rec + 1 <= p.cap_records) p.record_offsets[rec + 1] = f + 1;
                 ++lr;
                 col = 0;
@@ -853,6 +884,28 @@ __global__ void parse_init(Params p, size_t nwords)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     for (size_t k = i; k < nwords; k += (size_t)gridDim.x * blockDim.x) p.words[k] = 0ull;
+    if (i < 256) {
+        // per-byte transition rows from the DFA's group table (Table 1 layout):
+        // next state of every state, and (next*8 | tag<<6) of every state
+        const uint32_t b = (uint32_t)i;
+        const uint32_t g = p.group_of[b];
+        uint32_t lo = 0, hi = 0, clo = 0, chi = 0;
+        for (int s = 0; s < 8; ++s) {
+            const bool real = s < p.num_states;
+            const uint32_t nx = real ? p.next[g][s] : (uint32_t)s;
+            const uint32_t tg = real ? p.tag[g][s] : 0u;
+            const uint32_t cb = (nx * 8u) | (tg << 6);
+            if (s < 4) { lo |= nx << (8 * s); clo |= cb << (8 * s); }
+            else { hi |= nx << (8 * (s - 4)); chi |= cb << (8 * (s - 4)); }
+        }
+        if (p.num_states > 4) {
+            p.tables[2 * b] = lo; p.tables[2 * b + 1] = hi;
+            p.tables[512 + 2 * b] = clo; p.tables[512 + 2 * b + 1] = chi;
+        } else {
+            p.tables[b] = lo;
+            p.tables[512 + b] = clo;
+        }
+    }
     if (i == 0) {
         *p.counter = 0u;
         pp_result_t* r = p.result;
@@ -920,7 +973,7 @@ extern "C" size_t pp_workspace_size(int64_t n, const pp_options_t* opts)
     if (n < 0 || !shape_of(opts, &sh)) return 0;
     const int64_t tb = (int64_t)sh.nt * sh.b;
     const int64_t tiles = (n + tb - 1) / tb;
-    return 256 + (size_t)tiles * kWordsPerTile * sizeof(u64);
+    return kWsHeader + kWsTables + (size_t)tiles * kWordsPerTile * sizeof(u64);
 }
 
 extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
@@ -951,7 +1004,8 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     p.column_ids = out->d_column_ids;
     p.result = out->d_result;
     p.counter = (unsigned int*)d_ws;
-    p.words = (u64*)((char*)d_ws + 256);
+    p.tables = (uint32_t*)((char*)d_ws + kWsHeader);
+    p.words = (u64*)((char*)d_ws + kWsHeader + kWsTables);
     const int64_t tb = (int64_t)sh.nt * sh.b;
     const int64_t tiles = (n + tb - 1) / tb;
     if (tiles > 0x7fffffff) return PP_ERR_UNSUPPORTED;
@@ -983,7 +1037,7 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     }
     hipStream_t s = (hipStream_t)stream;
     const size_t nwords = (size_t)tiles * kWordsPerTile;
-    const int init_blocks = (int)std::min<size_t>(1024, (nwords + 255) / 256 + 1);
+    const int init_blocks = (int)std::min<size_t>(1024, std::max<size_t>(1, (nwords + 255) / 256));
     hipLaunchKernelGGL(parse_init, dim3(init_blocks), dim3(256), 0, s, p, nwords);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
     if (tiles == 0) return PP_OK;

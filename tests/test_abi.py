@@ -37,10 +37,11 @@ def test_no_oracle_in_product_library():
 
 
 def test_workspace_size_and_status_text():
-    assert pp.workspace_size(0) == 256
-    assert pp.workspace_size(32768) == 256 + 8 * 8          # default: 512 threads x 64 B
-    assert pp.workspace_size(32769) == 256 + 2 * 8 * 8
-    assert pp.workspace_size(1 << 20, pp.options(16, 256)) == 256 + 256 * 8 * 8
+    head = 256 + 4096  # ticket counter, byte tables
+    assert pp.workspace_size(0) == head
+    assert pp.workspace_size(32768) == head + 8 * 8          # default: 512 threads x 64 B
+    assert pp.workspace_size(32769) == head + 2 * 8 * 8
+    assert pp.workspace_size(1 << 20, pp.options(16, 256)) == head + 256 * 8 * 8
     assert pp.workspace_size(1 << 20, pp.options(48, 256)) == 0
     assert pp.lib().pp_status_str(0) == b"ok"
     assert pp.lib().pp_status_str(-2) == b"invalid DFA"
