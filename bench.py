@@ -82,7 +82,12 @@ def main():
         for _ in range(args.profile_steps):
             call.launch(stream)
         torch.cuda.synchronize()
-        print("[bench] profile launches done", file=sys.stderr, flush=True)
+        # reference for the HBM byte counters: one device copy of exactly 2^30 bytes
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print("[bench] profile launches done (plus one 1 GiB device copy)", file=sys.stderr, flush=True)
         return
 
     for _ in range(args.warmup):

@@ -38,9 +38,9 @@ __device__ inline bool conv_int64(const Src& src, int64_t b, int64_t e, int64_t*
 }
 
 // ---- calendar ----------------------------------------------------------------
-__device__ inline bool is_leap(int64_t y) { return (y % 4 == 0 && y % 100 != 0) || y % 400 == 0; }
+__device__ __forceinline__ bool is_leap(int64_t y) { return (y % 4 == 0 && y % 100 != 0) || y % 400 == 0; }
 
-__device__ inline int days_in_month(int64_t y, int64_t m)
+__device__ __forceinline__ int days_in_month(int64_t y, int64_t m)
 {
     // 30 + (m + m/8) % 2 gives 31/30 alternating with the July/August switch;
     // February is fixed up below.
@@ -53,7 +53,7 @@ __device__ inline int days_in_month(int64_t y, int64_t m)
 // era/day-of-era method ("chrono-compatible low-level date algorithms"):
 // shift the year to start in March so the leap day is last, split into
 // 400-year eras of 146097 days, and count within the era.
-__device__ inline int64_t days_from_civil(int64_t y, int64_t m, int64_t d)
+__device__ __forceinline__ int64_t days_from_civil(int64_t y, int64_t m, int64_t d)
 {
     y -= m <= 2;
     const int64_t era = (y >= 0 ? y : y - 399) / 400;
@@ -112,7 +112,7 @@ __device__ inline bool conv_timestamp(const Src& src, int64_t b, int64_t e, int6
 // rounding to 53 bits with ties to even (the "simple decimal conversion"
 // method; 800 retained digits plus a sticky flag decide every halfway case).
 
-__device__ inline double exact_pow10(int k)
+__device__ __forceinline__ double exact_pow10(int k)
 {
     // 10^k for 0 <= k <= 22 by binary exponentiation. Every partial product
     // is some 10^j with j <= 22, exactly representable in binary64, so each

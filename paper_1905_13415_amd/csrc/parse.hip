@@ -319,15 +319,23 @@ __device__ inline int store_field(const Params& p, const ColDesc* cols, const By
     const int64_t off = begin - src.tile_start;
     const int len = (int)(end - begin);
     if (off >= 0 && len <= kWin) {  // short field inside the tile: parse from registers
-        const Win x = load_win(reinterpret_cast<const uint32_t*>(src.lds), src.tile_size, (int)off);
-        if (ty == PP_FLOAT64) {
-            double dv = 0.0;
-            r = win_float64(x, len, &dv);
-            bits = __builtin_bit_cast(u64, dv);
+        const uint32_t* words = reinterpret_cast<const uint32_t*>(src.lds);
+        if (ty == PP_FLOAT64 || ty == PP_INT64) {
+            const Win x = load_win(words, src.tile_size, (int)off + len - kWin);  // right-aligned
+            const bool neg = src.lds[off] == '-';
+            if (ty == PP_FLOAT64) {
+                double dv = 0.0;
+                r = win_float64(x, len, neg, &dv);
+                bits = __builtin_bit_cast(u64, dv);
+            } else {
+                int64_t iv = 0;
+                r = win_int64(x, len, neg, &iv);
+                bits = (u64)iv;
+            }
         } else {
+            const Win x = load_win(words, src.tile_size, (int)off);
             int64_t iv = 0;
-            if (ty == PP_INT64) r = win_int64(x, len, &iv);
-            else if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
+            if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
             else r = win_date(x, len, &iv);
             bits = (u64)iv;
         }
@@ -376,13 +384,15 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 
     __shared__ uint32_t s_tnext[NS8 ? 512 : 256];  // byte -> next state of every state
     __shared__ uint32_t s_tcomb[NS8 ? 512 : 256];  // byte -> per state (next*8 | tag<<6)
-    __shared__ __align__(16) uint8_t s_bytes[TILE];
+    __shared__ __align__(16) uint8_t s_bytes[TILE + 32];  // +32: register windows read past the end
     __shared__ uint16_t s_pos[FCAP];     // tile-relative delimiter positions
     __shared__ uint16_t s_colid[FCAP];   // column of the field each delimiter closes
     __shared__ uint16_t s_recend[RCAP];  // local field index of each record delimiter
     __shared__ uint32_t s_ctl[TILE / 32];  // control-symbol bitmap of the tile
     __shared__ uint8_t s_types[PP_MAX_COLUMNS];
     __shared__ ColDesc s_cols[PP_MAX_COLUMNS];
+    __shared__ ColDesc s_cb[PP_MAX_COLUMNS];  // column outputs offset to this tile's first record
+    __shared__ uint32_t s_anyctl;
     __shared__ SV<NS8> s_wsv[NW];
     __shared__ Cnt s_wcnt[NW];
     __shared__ uint32_t s_tile, s_s0, s_final, s_last_sa, s_ctl_last;
@@ -397,6 +407,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     if (tid == 0) {
         s_tile = atomicAdd(p.counter, 1u);  // tiles in start order: predecessors are running
         s_lasttid = -1;
+        s_anyctl = 0;
         s_err = 0;
         s_ragged = 0;
     }
@@ -592,6 +603,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         mine.col = popc(dmask);
     }
     mine.last = vend ? (uint32_t)(tile_len + 1) : (dmask ? (uint32_t)(c0 + msb(dmask) + 1) : 0u);
+    if (cmask) s_anyctl = 1u;
     if constexpr (B == 64) {
         s_ctl[2 * tid] = (uint32_t)cmask;
         s_ctl[2 * tid + 1] = (uint32_t)(cmask >> 32);
@@ -747,16 +759,22 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         // ---- 6. emit structure through LDS --------------------------------------------------
         {
             uint32_t L = cex.nf, lr = cex.nr;
-            int64_t col = (cex.col & kCAbs) ? (int64_t)(cex.col & ~kCAbs) : C0 + (int64_t)cex.col;
-            M m = dmask;
-            while (m) {
-                const int i = B > 32 ? __ffsll((long long)m) - 1 : __ffs((int)m) - 1;
-                m &= m - 1;
-                s_pos[L] = (uint16_t)(c0 + i);
-                s_colid[L] = (uint16_t)col;
-                if ((rmask >> i) & 1u) { s_recend[lr++] = (uint16_t)L; col = 0; }
-                else ++col;
-                ++L;
+            uint32_t col = (cex.col & kCAbs) ? (cex.col & ~kCAbs) : (uint32_t)C0 + cex.col;
+#pragma unroll
+            for (int h = 0; h < (B > 32 ? 2 : 1); ++h) {
+                uint32_t m = (uint32_t)(dmask >> (32 * h));
+                const uint32_t rm = (uint32_t)(rmask >> (32 * h));
+                const uint32_t base = (uint32_t)c0 + 32u * h;
+                while (m) {
+                    const uint32_t i = (uint32_t)__builtin_ctz(m);
+                    m &= m - 1;
+                    const bool isr = (rm >> i) & 1u;
+                    s_pos[L] = (uint16_t)(base + i);
+                    s_colid[L] = (uint16_t)col;
+                    if (isr) s_recend[lr++] = (uint16_t)L;
+                    col = isr ? 0u : col + 1u;
+                    ++L;
+                }
             }
             if (vend) {
                 s_pos[L] = (uint16_t)tile_len;
@@ -764,45 +782,121 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
                 s_recend[lr] = (uint16_t)L;
             }
         }
-        __syncthreads();
-        for (int k = tid; k < Ft; k += NT) {
-            const int64_t f = F0 + 1 + k;
-            if (f <= p.cap_fields) p.field_offsets[f] = tile_start + s_pos[k] + 1;
-            if (f - 1 < p.cap_fields) p.column_ids[f - 1] = s_colid[k];
+        if (tid < ncols) {  // column outputs as seen from this tile's first record
+            ColDesc d = s_cols[tid];
+            d.values = (char*)d.values + R0 * 8;
+            d.valid = d.valid + R0;
+            d.str_end = d.str_end + R0;
+            s_cb[tid] = d;
         }
-        for (int k = tid; k < Rt; k += NT) {
-            const int64_t r = R0 + 1 + k;
-            if (r <= p.cap_records) p.record_offsets[r] = F0 + s_recend[k] + 1;
+        __syncthreads();
+        {
+            const int64_t roomf = p.cap_fields - F0;
+            const int kf = roomf < Ft ? (int)(roomf < 0 ? 0 : roomf) : Ft;
+            int64_t* const fo = p.field_offsets + F0 + 1;
+            int32_t* const ci = p.column_ids + F0;
+            for (int k = tid; k < kf; k += NT) {
+                fo[k] = tile_start + 1 + s_pos[k];
+                ci[k] = s_colid[k];
+            }
+            const int64_t roomr = p.cap_records - R0;
+            const int kr = roomr < Rt ? (int)(roomr < 0 ? 0 : roomr) : Rt;
+            int64_t* const ro = p.record_offsets + R0 + 1;
+            for (int k = tid; k < kr; k += NT) ro[k] = F0 + 1 + s_recend[k];
         }
 
         // ---- 7. typed columns, column-major over (column, local record) ------------------
-        const int nrec = Rt + 1;  // records closed here plus the open one
-        const int items = nrec * ncols;
-        const float rcp = 1.0f / (float)nrec;
-        for (int q = tid; q < items; q += NT) {
-            int c = (int)((float)q * rcp);
-            if (c * nrec > q) --c;
-            else if ((c + 1) * nrec <= q) ++c;
-            const int lr = q - c * nrec;
-            const int first = lr == 0 ? 0 : s_recend[lr - 1] + 1;
-            const int64_t cf = lr == 0 ? C0 : 0;
-            const int last = lr < Rt ? (int)s_recend[lr] : Ft - 1;
-            const int64_t rec = R0 + lr;
-            if (c == 0 && lr < Rt && cf + (last - first + 1) != ncols) ++nragged;
-            if (c < cf) continue;
-            const int ty = s_types[c];
-            if (ty == PP_SKIP) continue;
-            const int64_t Lz = first + (c - cf);
-            if (Lz > last) {
-                if (lr < Rt) store_missing(p, s_cols, c, ty, rec);  // missing column of a short record
-                continue;
+        const uint32_t nrec = (uint32_t)Rt + 1u;  // records closed here plus the open one
+        const uint32_t items = nrec * (uint32_t)ncols;
+        const int64_t roomr = p.cap_records - R0;
+        const uint32_t lr_cap = roomr <= 0 ? 0u : (roomr > (int64_t)nrec ? nrec : (uint32_t)roomr);
+        const bool anyctl = s_anyctl != 0;
+        const uint32_t* const words = reinterpret_cast<const uint32_t*>(s_bytes);
+        const uint32_t dq = (uint32_t)NT / nrec, dr = (uint32_t)NT % nrec;
+        uint32_t c = (uint32_t)tid / nrec, lr = (uint32_t)tid % nrec;
+        for (uint32_t q = tid; q < items; q += NT) {
+            const uint32_t first = lr ? s_recend[lr - 1] + 1u : 0u;
+            const uint32_t end1 = lr < (uint32_t)Rt ? s_recend[lr] + 1u : (uint32_t)Ft;  // one past the last field
+            const uint32_t cf = lr ? 0u : (uint32_t)C0;
+            if (c == 0 && lr < (uint32_t)Rt && cf + end1 - first != (uint32_t)ncols) ++nragged;
+            const uint32_t ty = s_types[c];
+            if (c >= cf && ty != PP_SKIP) {
+                const uint32_t L = first + c - cf;
+                if (L >= end1) {
+                    if (lr < (uint32_t)Rt && lr < lr_cap) {  // missing column of a short record
+                        const ColDesc cd = s_cb[c];
+                        ((u64*)cd.values)[lr] = 0;
+                        cd.valid[lr] = 0;
+                        if (ty == PP_STRING) cd.str_end[lr] = 0;
+                    }
+                } else if (L == 0) {  // may begin in an earlier tile: general path
+                    const int64_t e = tile_start + s_pos[0];
+                    const int64_t bb = last_has ? last_pos + 1 : 0;
+                    const bool cfst = e > bb && ctl_at_begin(bb);
+                    const bool clst = e > bb && ctl_at_end(e);
+                    nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, bb, e, cfst, clst);
+                } else {
+                    int bb = s_pos[L - 1] + 1, ee = s_pos[L];
+                    if (anyctl && ee > bb) {  // strip enclosing control symbols
+                        if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
+                        if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
+                    }
+                    const ColDesc cd = s_cb[c];
+                    const bool st = lr < lr_cap;
+                    if (ty == PP_STRING) {
+                        if (st) {
+                            ((int64_t*)cd.values)[lr] = tile_start + bb;
+                            cd.str_end[lr] = tile_start + ee;
+                            cd.valid[lr] = 1;
+                        }
+                    } else if (ee == bb) {  // empty: the column default, not an error
+                        if (st) {
+                            ((u64*)cd.values)[lr] = 0;
+                            cd.valid[lr] = 0;
+                        }
+                    } else {
+                        const int len = ee - bb;
+                        int r = -1;
+                        u64 bits = 0;
+                        if (len <= kWin) {
+                            const Win x = load_win_padded(words, bb);
+                            if (ty == PP_FLOAT64) {
+                                double dv = 0.0;
+                                r = ser_float64(x, len, &dv);
+                                bits = __builtin_bit_cast(u64, dv);
+                            } else {
+                                int64_t iv = 0;
+                                if (ty == PP_INT64) r = ser_int64(x, len, &iv);
+                                else if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
+                                else r = win_date(x, len, &iv);
+                                bits = (u64)iv;
+                            }
+                        }
+                        if (r < 0) {
+                            const int64_t gb = tile_start + bb, ge = tile_start + ee;
+                            if (ty == PP_FLOAT64) {
+                                double dv = 0.0;
+                                r = conv_float64(src, gb, ge, &dv);
+                                bits = __builtin_bit_cast(u64, dv);
+                            } else {
+                                int64_t iv = 0;
+                                if (ty == PP_INT64) r = conv_int64(src, gb, ge, &iv);
+                                else if (ty == PP_TIMESTAMP_S) r = conv_timestamp(src, gb, ge, &iv);
+                                else r = conv_date(src, gb, ge, &iv);
+                                bits = (u64)iv;
+                            }
+                        }
+                        nerr += r == 0;
+                        if (st) {
+                            ((u64*)cd.values)[lr] = r ? bits : 0ull;
+                            cd.valid[lr] = (uint8_t)r;
+                        }
+                    }
+                }
             }
-            const int L = (int)Lz;
-            const int64_t e = tile_start + s_pos[L];
-            const int64_t b = L == 0 ? (last_has ? last_pos + 1 : 0) : tile_start + s_pos[L - 1] + 1;
-            const bool cfst = e > b && ctl_at_begin(b);
-            const bool clst = e > b && ctl_at_end(e);
-            nerr += store_field(p, s_cols, src, c, ty, rec, b, e, cfst, clst);
+            lr += dr;
+            c += dq;
+            if (lr >= nrec) { lr -= nrec; ++c; }
         }
         if (ncols == 0 && tid == 0) nragged = Rt;
     } else {
