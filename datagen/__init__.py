@@ -28,6 +28,7 @@ import numpy as np
 
 from . import dialects  # noqa: F401
 from .dialects import (Dfa, Schema, SCHEMA_C1, SCHEMA_C2, SCHEMA_C3, SCHEMA_LOG12)
+from .dialects import SCHEMA_C1 as SCHEMA_MIXED
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gen.c")
@@ -191,3 +192,58 @@ def log(seed: int, nbytes: int, delim: bytes = b" ", with_truth: bool = False) -
 
 
 SCHEMAS = {"c1": SCHEMA_C1, "c2": SCHEMA_C2, "c3": SCHEMA_C3, "log": SCHEMA_LOG12}
+
+
+# ---- the batched workload: many buffers, mixed dialects -----------------------
+
+# DFA family of 3 to 8 states and the content style each one parses:
+# (dfa factory name, generator kind, quoting style)
+C4_FAMILY = [("s3", K_MIXED, 3), ("csv4", K_MIXED, 1), ("s5", K_MIXED, 1),
+             ("paper6", K_MIXED, 1), ("s7", K_MIXED, 2), ("s8", K_LOG, 0)]
+C4_DELIMS = [b",", b"\t", b"|"]
+
+
+@dataclass
+class BufferSpec:
+    index: int
+    dfa_name: str
+    delim: bytes
+    kind: int
+    qstyle: int
+    nbytes: int   # size limit (whole records up to it)
+    seed: int
+
+    @property
+    def dialect(self) -> int:
+        return [n for n, _, _ in C4_FAMILY].index(self.dfa_name) * len(C4_DELIMS) + C4_DELIMS.index(self.delim)
+
+
+def c4_dialects():
+    """The 18 dialects (6 DFAs x 3 delimiters), in dialect-index order."""
+    out = []
+    for name, _, _ in C4_FAMILY:
+        for d in C4_DELIMS:
+            out.append(dialects.ALL_DFAS[name](d))
+    return out
+
+
+def c4_plan(seed: int = SEED_BASE + 3, count: int = 4096, lo: int = 1 << 10, hi: int = 64 << 20):
+    """Buffer sizes log-uniform in [lo, hi] and a uniformly drawn dialect per
+    buffer (numpy PCG64 seeded with ``seed``)."""
+    rng = np.random.default_rng(seed)
+    sizes = np.exp(rng.uniform(np.log(lo), np.log(hi), size=count)).astype(np.int64)
+    fam = rng.integers(0, len(C4_FAMILY), size=count)
+    dl = rng.integers(0, len(C4_DELIMS), size=count)
+    plan = []
+    for i in range(count):
+        name, kind, q = C4_FAMILY[int(fam[i])]
+        plan.append(BufferSpec(i, name, C4_DELIMS[int(dl[i])], kind, q, int(sizes[i]), seed * 7919 + i))
+    return plan
+
+
+def c4_buffer(spec: BufferSpec, threads: int = 16) -> Generated:
+    if spec.kind == K_LOG:
+        return generate(K_LOG, spec.seed, max_bytes=spec.nbytes, delim=spec.delim, block_records=4096,
+                        threads=threads)
+    return generate(K_MIXED, spec.seed, max_bytes=spec.nbytes, delim=spec.delim, qstyle=spec.qstyle,
+                    block_records=4096, threads=threads)

@@ -85,8 +85,9 @@ def _table(rows: Sequence[str], states: Sequence[str]):
     return nxt, tg
 
 
-def paper6() -> Dfa:
-    """The CSV DFA of Table 1 (states EOR, ENC, FLD, EOF, ESC, INV).
+def paper6(delim: bytes = b",") -> Dfa:
+    """The CSV DFA of Table 1 (states EOR, ENC, FLD, EOF, ESC, INV); the field
+    delimiter group holds ',' as printed, or another delimiter byte.
 
     Next states are Table 1 verbatim. The paper gives no tag table, only that
     tags follow the format's rules (Sec. 3.1); the reading used here: a
@@ -104,7 +105,7 @@ def paper6() -> Dfa:
         "FLD/D ENC/D FLD/D FLD/D INV/D INV/D",  # 3: other
     ]
     nxt, tg = _table(rows, states)
-    return Dfa("paper6", states, [b"\n", b'"', b","], nxt, tg, start_state=0,
+    return Dfa("paper6", states, [b"\n", b'"', delim], nxt, tg, start_state=0,
                accept=[0, 2, 3, 4], invalid_state=5)
 
 

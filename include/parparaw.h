@@ -44,6 +44,7 @@ typedef int32_t pp_status_t;
 #define PP_ERR_WORKSPACE (-4)   /* workspace smaller than pp_workspace_size() */
 #define PP_ERR_HIP (-5)         /* a HIP launch failed */
 #define PP_ERR_UNSUPPORTED (-6) /* a combination this build does not support */
+#define PP_ERR_BUDGET (-7)      /* a request larger than the server's whole device budget */
 
 /* Symbol tags (Sec. 3.1: record delimiter, field delimiter, control symbol,
  * or part of a field's value). */
@@ -125,10 +126,14 @@ typedef struct {
     const int32_t* types; /* host array of ncols PP_* types */
 } pp_schema_t;
 
-/* Launch shape. bytes_per_thread is the chunk size of Sec. 3.1. */
+/* Launch shape: a workgroup of block_threads threads parses a tile of
+ * block_threads * bytes_per_thread bytes; bytes_per_thread is the chunk size
+ * of Sec. 3.1. Supported (threads x bytes): 512x64 (the default), 256x64,
+ * 512x32, 256x32, 256x16. Zero fields take the default. Any shape gives
+ * identical outputs. */
 typedef struct {
-    int32_t bytes_per_thread; /* 0 = default; supported: 16, 32 */
-    int32_t block_threads;    /* 0 = default; supported: 256 */
+    int32_t bytes_per_thread;
+    int32_t block_threads;
 } pp_options_t;
 
 /* Device scratch that pp_parse needs for an input of n bytes (tile counter
@@ -150,6 +155,118 @@ pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
 
 /* Static text for a pp_status_t. */
 const char* pp_status_str(pp_status_t s);
+
+/* ---- batched form ---------------------------------------------------------
+ * Many independent buffers, each with its own DFA (dialect), schema and
+ * outputs, parsed by one kernel launch: workgroups take (buffer, tile) work
+ * items from one ticket counter in buffer-then-tile order, and each
+ * buffer's tiles run the same pipeline as pp_parse (Sec. 3.1-3.3) with their
+ * own lookback words. Results per buffer are identical to pp_parse's.
+ *
+ * Lifecycle: pp_batch_create (host only: validates, builds descriptor tables)
+ * -> pp_batch_workspace_size -> pp_batch_bind (uploads the descriptors into
+ * the caller's device workspace on a stream) -> pp_batch_launch any number of
+ * times, or capture it once with pp_batch_graph_create and replay with
+ * pp_batch_graph_launch. Launches allocate nothing and do not synchronise the
+ * host. Inputs, outputs and workspace must stay valid while launches run; a
+ * launch overwrites every output of every buffer. */
+typedef struct {
+    const uint8_t* d_in;   /* device bytes of this buffer (any alignment) */
+    int64_t n;             /* its length */
+    int32_t dialect;       /* index into the dfas array of pp_batch_create */
+    int32_t ncols;         /* 0..PP_MAX_COLUMNS */
+    const int32_t* types;  /* host array of ncols PP_* types (copied) */
+    pp_outputs_t out;      /* its device outputs (pointer arrays are copied) */
+} pp_batch_item_t;
+
+typedef struct pp_batch pp_batch_t;
+typedef struct pp_batch_graph pp_batch_graph_t;
+
+pp_status_t pp_batch_create(const pp_dfa_t* dfas, int32_t ndfas, const pp_batch_item_t* items,
+                            int32_t count, const pp_options_t* opts, pp_batch_t** batch);
+size_t pp_batch_workspace_size(const pp_batch_t* batch);
+/* Number of (buffer, tile) work items of the batch. */
+int64_t pp_batch_num_tiles(const pp_batch_t* batch);
+pp_status_t pp_batch_bind(pp_batch_t* batch, void* d_ws, size_t ws_bytes, void* stream);
+pp_status_t pp_batch_launch(const pp_batch_t* batch, void* stream);
+pp_status_t pp_batch_graph_create(const pp_batch_t* batch, pp_batch_graph_t** graph);
+pp_status_t pp_batch_graph_launch(pp_batch_graph_t* graph, void* stream);
+void pp_batch_graph_destroy(pp_batch_graph_t* graph);
+void pp_batch_destroy(pp_batch_t* batch);
+
+/* ---- serving form ---------------------------------------------------------
+ * A request loop in front of the batched form, for host-resident inputs: the
+ * streaming setting of Sec. 4.4 (transfers overlapped with parsing) with
+ * continuous batching. pp_server_create carves one device allocation of
+ * hbm_budget_bytes (the only allocation the server makes) and starts a
+ * scheduler thread. Requests are admitted in arrival order while a slot is
+ * free and their input plus output blocks fit; admitted inputs are copied
+ * from the caller's pinned host memory on copy streams; whenever a compute
+ * stream is free, every request whose copy has finished joins one batched
+ * launch there, so requests that arrive while others are on the device join
+ * the next launch. A request whose outputs overflow the capacities it gave is
+ * parsed again with the exact sizes (once). Outputs stay in device memory
+ * until pp_server_release. Outputs of a request are identical to pp_parse's
+ * on the same bytes, whatever else is in flight.
+ *
+ * Thread-safety: submit, poll, wait, release and get_stats may be called from
+ * any thread; destroy must not race with the others. */
+typedef struct pp_server pp_server_t;
+
+typedef struct {
+    size_t hbm_budget_bytes; /* device memory the server holds (>= 64 MiB) */
+    int32_t max_slots;       /* admitted and not yet released requests, at most (>= 1) */
+    int32_t copy_streams;    /* 1..4 host-to-device copy streams (0: 2) */
+    int32_t compute_streams; /* 1..2 streams running batched launches (0: 2) */
+    int32_t max_batch;       /* requests per batched launch (0: max_slots) */
+    pp_options_t opts;       /* launch shape (zeros: default) */
+} pp_server_config_t;
+
+typedef struct {
+    const uint8_t* h_in;   /* host bytes, pinned (hipHostMalloc); the caller keeps
+                              them unchanged until the request completes */
+    int64_t n;
+    int32_t dialect;       /* index into the dfas of pp_server_create */
+    int32_t ncols;         /* 0..PP_MAX_COLUMNS */
+    const int32_t* types;  /* host array of ncols PP_* types (copied) */
+    int64_t cap_records;   /* output capacities of the first attempt */
+    int64_t cap_fields;
+} pp_server_request_t;
+
+typedef struct {
+    uint64_t id;
+    int64_t n;
+    pp_result_t result;  /* status CAPACITY only if the exact sizes exceed the budget */
+    pp_outputs_t out;    /* device pointers into the server's memory, valid until
+                            pp_server_release; all NULL if no outputs were kept */
+    int64_t t_arrival_ns;     /* host steady clock: submit */
+    int64_t t_admit_ns;       /* admitted (memory carved, copy enqueued) */
+    int64_t t_h2d_done_ns;    /* copy finished on the device */
+    int64_t t_parse_done_ns;  /* its batched launch finished on the device */
+} pp_server_completion_t;
+
+typedef struct {
+    int64_t submitted, completed, reparsed;
+    int64_t batches, batched_requests, max_batch;
+    int64_t bytes_completed;
+    int64_t arena_bytes, arena_used_bytes, arena_peak_bytes;
+    int64_t pending;
+    int64_t hip_error; /* nonzero: a HIP call failed; the server has stopped */
+} pp_server_stats_t;
+
+pp_status_t pp_server_create(const pp_server_config_t* cfg, const pp_dfa_t* dfas, int32_t ndfas,
+                             pp_server_t** server);
+/* PP_ERR_BUDGET: the request's input plus outputs exceed the whole budget. */
+pp_status_t pp_server_submit(pp_server_t* server, const pp_server_request_t* req, uint64_t* id);
+/* Copies up to max completions, oldest first, into out; *got = how many. */
+pp_status_t pp_server_poll(pp_server_t* server, pp_server_completion_t* out, int32_t max, int32_t* got);
+/* Blocks until a completion is waiting or timeout_us passes. */
+pp_status_t pp_server_wait(pp_server_t* server, int64_t timeout_us);
+/* Frees a completed request's outputs and slot. */
+pp_status_t pp_server_release(pp_server_t* server, uint64_t id);
+pp_status_t pp_server_get_stats(pp_server_t* server, pp_server_stats_t* stats);
+/* Waits for the device work in flight, then frees everything. */
+void pp_server_destroy(pp_server_t* server);
 
 #ifdef __cplusplus
 }

@@ -16,7 +16,7 @@ from typing import List, Optional, Sequence
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
-SOURCES = [os.path.join(_HERE, "csrc", "parse.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip")]
 
 PP_OK = 0
 STATUS_TEXT = {0: "ok", -1: "invalid argument", -2: "invalid DFA", -3: "invalid schema",
@@ -86,6 +86,24 @@ def lib():
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
         L.pp_status_str.restype = ctypes.c_char_p
         L.pp_status_str.argtypes = [ctypes.c_int32]
+        L.pp_batch_create.restype = ctypes.c_int32
+        L.pp_batch_create.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.POINTER(P)]
+        L.pp_batch_workspace_size.restype = ctypes.c_size_t
+        L.pp_batch_workspace_size.argtypes = [P]
+        L.pp_batch_num_tiles.restype = ctypes.c_int64
+        L.pp_batch_num_tiles.argtypes = [P]
+        L.pp_batch_bind.restype = ctypes.c_int32
+        L.pp_batch_bind.argtypes = [P, P, ctypes.c_size_t, P]
+        L.pp_batch_launch.restype = ctypes.c_int32
+        L.pp_batch_launch.argtypes = [P, P]
+        L.pp_batch_graph_create.restype = ctypes.c_int32
+        L.pp_batch_graph_create.argtypes = [P, ctypes.POINTER(P)]
+        L.pp_batch_graph_launch.restype = ctypes.c_int32
+        L.pp_batch_graph_launch.argtypes = [P, P]
+        L.pp_batch_graph_destroy.restype = None
+        L.pp_batch_graph_destroy.argtypes = [P]
+        L.pp_batch_destroy.restype = None
+        L.pp_batch_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -209,3 +227,89 @@ def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
     call.launch(stream)
     out._call = call  # keep workspace alive until the caller synchronises
     return out
+
+
+class PpBatchItem(ctypes.Structure):
+    _fields_ = [("d_in", ctypes.c_void_p), ("n", ctypes.c_int64), ("dialect", ctypes.c_int32),
+                ("ncols", ctypes.c_int32), ("types", ctypes.c_void_p), ("out", PpOutputs)]
+
+
+def _check(rc, what):
+    if rc != PP_OK:
+        raise PpError(f"{what}: {STATUS_TEXT.get(rc, rc)}")
+
+
+class Batch:
+    """Many buffers with their own dialects and outputs in one
+    launch (pp_batch_*). ``items`` is a list of (d_in, dialect index, types,
+    Outputs); ``dfas`` the dialect list the indexes refer to."""
+
+    def __init__(self, dfas, items, opts: Optional[PpOptions] = None, stream=None):
+        import torch
+        L = lib()
+        self._dfas = (PpDfa * len(dfas))(*[dfa_struct(d) for d in dfas])
+        self._keep = []
+        arr = (PpBatchItem * max(len(items), 1))()
+        for i, (d_in, dialect, types, out) in enumerate(items):
+            n = int(d_in.numel())
+            nc = len(types)
+            t = (ctypes.c_int32 * max(nc, 1))(*types)
+            vp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.values])
+            mp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.valid])
+            ep = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.str_end])
+            self._keep += [t, vp, mp, ep]
+            arr[i].d_in = d_in.data_ptr() if n else None
+            arr[i].n = n
+            arr[i].dialect = dialect
+            arr[i].ncols = nc
+            arr[i].types = ctypes.cast(t, ctypes.c_void_p)
+            arr[i].out = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets),
+                                   _ptr(out.field_offsets), _ptr(out.column_ids),
+                                   ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
+                                   ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result))
+        self.items = items
+        h = ctypes.c_void_p()
+        _check(L.pp_batch_create(self._dfas, len(dfas), arr, len(items),
+                                 ctypes.byref(opts) if opts else None, ctypes.byref(h)), "pp_batch_create")
+        self.handle = h
+        self.num_tiles = int(L.pp_batch_num_tiles(h))
+        size = int(L.pp_batch_workspace_size(h))
+        dev = items[0][0].device if items else torch.device("cuda")
+        self.ws = torch.empty(max(size, 1), dtype=torch.uint8, device=dev)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(L.pp_batch_bind(h, self.ws.data_ptr(), self.ws.numel(), ctypes.c_void_p(stream.cuda_stream)),
+               "pp_batch_bind")
+        self.graph = None
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().pp_batch_launch(self.handle, ctypes.c_void_p(stream.cuda_stream)), "pp_batch_launch")
+
+    def capture(self):
+        g = ctypes.c_void_p()
+        _check(lib().pp_batch_graph_create(self.handle, ctypes.byref(g)), "pp_batch_graph_create")
+        self.graph = g
+
+    def replay(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        _check(lib().pp_batch_graph_launch(self.graph, ctypes.c_void_p(stream.cuda_stream)), "pp_batch_graph_launch")
+
+    def close(self):
+        L = lib()
+        if self.graph is not None:
+            L.pp_batch_graph_destroy(self.graph)
+            self.graph = None
+        if self.handle:
+            L.pp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,975 +1,41 @@
-// Single-pass parallel parse of delimiter-separated text on gfx950.
-//
-// One workgroup of NT threads owns a tile of NT*B input bytes; each thread
-// owns a chunk of B bytes (the per-thread chunks of Sec. 3.1). Per tile, in
-// one kernel:
-//   1. stage the tile in LDS with 16-byte loads; every thread keeps its
-//      chunk in registers;
-//   2. multi-state pass (Sec. 3.1): per chunk, one DFA instance per state,
-//      packed one byte per state in a register; a step is one v_perm_b32
-//      (<= 4 states) or two (<= 8 states) that looks every instance up in
-//      the byte's transition row: the chunk's state-transition vector;
-//   3. exclusive composition scan ((a o b)_i = b[a_i], Sec. 3.1): wave scan
-//      by shuffles, block scan through LDS, device scan by decoupled lookback
-//      (the single-pass scan the paper builds on, Sec. 2) in which one
-//      wavefront polls 64 predecessor tiles at a time;
-//   4. tag pass from the chunk's start state into register bitmaps of record
-//      delimiters, field delimiters and control symbols (Sec. 3.1);
-//   5. record counts (+), field counts (+), column carries (the abs/rel
-//      operator of Sec. 3.2) and the last delimiter position, scanned the
-//      same way;
-//   6. delimiter positions, column ids and record ends staged in LDS, then
-//      written coalesced as field offsets, column ids and record offsets;
-//   7. typed conversion (Sec. 3.3): the tile's (column, record) pairs are
-//      visited column-major, so a wavefront converts one column's type and
-//      its stores into that typed column are contiguous. This takes the place
-//      of the paper's radix-sort partition by column tag: the pair addresses
-//      the output slot directly.
-// Tiles with more fields or records than the LDS staging holds take a
-// per-thread path for steps 6-7 that gives the same outputs.
-// The input is read from HBM once; per-symbol metadata never leaves the chip.
+// Single-buffer launch of the parse pipeline (pp_parse): one workgroup per
+// tile, tiles handed out in start order by an atomic ticket so that every
+// predecessor a tile waits on in the lookback is already running.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
 #include <algorithm>
 #include <cstring>
-#include <type_traits>
 
-#include "convert.h"
-#include "convert_fast.h"
 #include "parparaw.h"
+#include "tile.h"
 
 namespace pp {
 
-typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
-typedef unsigned long long u64;
-constexpr uint32_t kTagControl = 1;
-
-struct ColDesc {
-    void* values;
-    uint8_t* valid;
-    int64_t* str_end;
-};
-
+// Kernel arguments: the tile arguments plus what parse_init needs to build
+// the workspace (DFA group tables and column descriptors).
 struct Params {
-    const uint8_t* in;
-    int64_t n;
-    int64_t cap_records;
-    int64_t cap_fields;
-    int64_t* record_offsets;
-    int64_t* field_offsets;
-    int32_t* column_ids;
-    pp_result_t* result;
-    u64* words;             // kWordsPerTile per tile
+    TileArgs a;
     unsigned int* counter;  // tile ticket
-    uint32_t* tables;       // 2 x 512 dwords: byte -> next states, byte -> (next*8 | tag<<6) per state
-    int32_t num_tiles;
-    int32_t ncols;
-    int32_t num_states;
-    int32_t start_state;
-    int32_t invalid_state;
-    uint32_t accept_mask;
+    uint32_t* tables;       // workspace copy of the byte tables (a.tables)
+    ColDesc* colws;         // workspace copy of the column descriptors (a.cols)
     uint8_t group_of[256];
     uint8_t next[PP_MAX_GROUPS][PP_MAX_STATES];
     uint8_t tag[PP_MAX_GROUPS][PP_MAX_STATES];
-    uint8_t types[PP_MAX_COLUMNS];
     ColDesc cols[PP_MAX_COLUMNS];
 };
 
-// ---- lookback words ----------------------------------------------------------
-// Every word is self-contained, [status:2 | payload:62], written once per
-// state by relaxed agent-scope atomics, so no ordering with other memory is
-// needed. Aggregates and inclusive prefixes of the counts live in separate
-// words: an aggregate is never overwritten, so a reader always finds either
-// all four inclusive words or both aggregate words of a tile.
-constexpr int kWordsPerTile = 8;
-// workspace: [ticket counter | pad] [byte tables, 4 KiB] [kWordsPerTile words per tile]
-constexpr size_t kWsHeader = 256, kWsTables = 4096;
-enum { W_STATE = 0, W_AGG0 = 1, W_AGG1 = 2, W_IREC = 3, W_IFLD = 4, W_ICOL = 5, W_ILAST = 6 };
-constexpr u64 kAgg = 1ull << 62, kIncl = 2ull << 62;
-constexpr u64 kPayload = (1ull << 62) - 1;
-// inclusive payloads: col = abs:1 @61 | value; last = has:1 @61 | ctl:1 @60 |
-// state after the delimiter:4 @56 | absolute position:56
-constexpr u64 kColAbs = 1ull << 61;
-constexpr u64 kColVal = kColAbs - 1;
-constexpr u64 kLastHas = 1ull << 61, kLastCtl = 1ull << 60;
-constexpr u64 kLastPos = (1ull << 56) - 1;
+// workspace: [ticket counter | pad] [byte tables, 4 KiB] [column descriptors] [kWordsPerTile words per tile]
+constexpr size_t kWsHeader = 256, kWsTables = 4096, kWsCols = PP_MAX_COLUMNS * sizeof(ColDesc);
 
-__device__ inline void publish(u64* w, u64 v)
-{
-    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline u64 peek(u64* w)
-{
-    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-}
-
-__device__ inline u64 ballot(bool x) { return __ballot(x); }
-
-__device__ inline u64 shfl_down64(u64 v, int d)
-{
-    uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)v, d);
-    uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)(v >> 32), d);
-    return ((u64)hi << 32) | lo;
-}
-
-__device__ inline u64 readlane0_64(u64 v)
-{
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
-    return ((u64)hi << 32) | lo;
-}
-
-// ---- state-transition vectors (Sec. 3.1) --------------------------------------
-// Entry i (byte i) is the end state of the instance that started in state i.
-// <= 4 states: one dword; <= 8 states: lo = states 0-3, hi = states 4-7.
-template <bool NS8>
-struct SV {
-    uint32_t lo, hi;
-};
-
-template <bool NS8>
-__device__ inline SV<NS8> sv_identity()
-{
-    return {0x03020100u, NS8 ? 0x07060504u : 0u};
-}
-
-// (a o b)_i = b[a_i]: v_perm_b32 picks byte sel of {src0:src1}, bytes 0-3
-// from src1 and 4-7 from src0.
-template <bool NS8>
-__device__ inline SV<NS8> compose(SV<NS8> a, SV<NS8> b)
-{
-    SV<NS8> r;
-    if constexpr (NS8) {
-        r.lo = __builtin_amdgcn_perm(b.hi, b.lo, a.lo);
-        r.hi = __builtin_amdgcn_perm(b.hi, b.lo, a.hi);
-    } else {
-        r.lo = __builtin_amdgcn_perm(0u, b.lo, a.lo);
-        r.hi = 0;
-    }
-    return r;
-}
-
-template <bool NS8>
-__device__ inline uint32_t sv_get(SV<NS8> v, uint32_t i)
-{
-    uint32_t w = (NS8 && i >= 4) ? v.hi : v.lo;
-    return (w >> ((i & 3) * 8)) & 0xffu;
-}
-
-template <bool NS8>
-__device__ inline uint32_t sv_to_nib(SV<NS8> v)
-{
-    uint32_t r = 0;
-    for (int i = 0; i < 4; ++i) r |= ((v.lo >> (8 * i)) & 0xfu) << (4 * i);
-    if constexpr (NS8)
-        for (int i = 0; i < 4; ++i) r |= ((v.hi >> (8 * i)) & 0xfu) << (16 + 4 * i);
-    return r;
-}
-
-template <bool NS8>
-__device__ inline SV<NS8> sv_from_nib(uint32_t x)
-{
-    SV<NS8> v{0u, 0u};
-    for (int i = 0; i < 4; ++i) v.lo |= ((x >> (4 * i)) & 0xfu) << (8 * i);
-    if constexpr (NS8)
-        for (int i = 0; i < 4; ++i) v.hi |= ((x >> (16 + 4 * i)) & 0xfu) << (8 * i);
-    return v;
-}
-
-template <bool NS8>
-__device__ inline SV<NS8> shfl_up_sv(SV<NS8> v, int d)
-{
-    SV<NS8> r;
-    r.lo = (uint32_t)__shfl_up((int)v.lo, d);
-    r.hi = NS8 ? (uint32_t)__shfl_up((int)v.hi, d) : 0u;
-    return r;
-}
-
-template <bool NS8>
-__device__ inline SV<NS8> shfl_down_sv(SV<NS8> v, int d)
-{
-    SV<NS8> r;
-    r.lo = (uint32_t)__shfl_down((int)v.lo, d);
-    r.hi = NS8 ? (uint32_t)__shfl_down((int)v.hi, d) : 0u;
-    return r;
-}
-
-// One DFA step through the combined table: state*8 -> next state*8.
-template <bool NS8>
-__device__ inline uint32_t step_state(const uint32_t* tcomb, uint32_t b, uint32_t s8)
-{
-    uint32_t x;
-    if constexpr (NS8) x = __builtin_amdgcn_ubfe(tcomb[2 * b + (s8 >> 5)], s8 & 31u, 8);
-    else x = __builtin_amdgcn_ubfe(tcomb[b], s8, 8);
-    return x & 0x38u;
-}
-
-// ---- count scan element within a tile (Sec. 3.2) ---------------------------------
-// nr: record delimiters; nf: delimiters (fields closed); col: column carry,
-// bit 31 = abs; last: tile-relative position + 1 of the last delimiter (0: none).
-struct Cnt {
-    uint32_t nr, nf, col, last;
-};
-constexpr uint32_t kCAbs = 1u << 31;
-
-__device__ inline Cnt cnt_combine(Cnt a, Cnt b)
-{
-    Cnt r;
-    r.nr = a.nr + b.nr;
-    r.nf = a.nf + b.nf;
-    r.col = (b.col & kCAbs) ? b.col : a.col + b.col;  // the abs/rel operator of Sec. 3.2
-    r.last = b.last ? b.last : a.last;
-    return r;
-}
-
-__device__ inline Cnt shfl_up_cnt(Cnt c, int d)
-{
-    return {(uint32_t)__shfl_up((int)c.nr, d), (uint32_t)__shfl_up((int)c.nf, d),
-            (uint32_t)__shfl_up((int)c.col, d), (uint32_t)__shfl_up((int)c.last, d)};
-}
-
-// ---- device-wide count prefix ------------------------------------------------------
-struct Tot {
-    u64 rec, fld, col, last;
-};
-
-__device__ inline Tot tot_combine(Tot a, Tot b)
-{
-    Tot r;
-    r.rec = a.rec + b.rec;
-    r.fld = a.fld + b.fld;
-    r.col = (b.col & kColAbs) ? b.col : a.col + b.col;
-    const u64 body = (b.last & kLastHas) ? b.last : a.last;
-    r.last = (body & ~kLastCtl) | (b.last & kLastCtl);  // control bit of the last byte: from b
-    return r;
-}
-
-__device__ inline Tot shfl_down_tot(Tot t, int d)
-{
-    return {shfl_down64(t.rec, d), shfl_down64(t.fld, d), shfl_down64(t.col, d), shfl_down64(t.last, d)};
-}
-
-// aggregate words: agg0 = nr:31 @31 | nf:31; agg1 = col:31 @31 | last:31 where
-// col = abs:1 @30 | value:30 and last = has:1 @30 | ctl:1 @29 | state after:4 @25 | pos in tile:25
-__device__ inline Tot tot_from_agg(u64 a0, u64 a1, int64_t tile_start)
-{
-    Tot t;
-    t.rec = (a0 >> 31) & 0x7fffffffull;
-    t.fld = a0 & 0x7fffffffull;
-    const u64 c = (a1 >> 31) & 0x7fffffffull;
-    t.col = ((c >> 30) & 1 ? kColAbs : 0ull) | (c & 0x3fffffffull);
-    const u64 l = a1 & 0x7fffffffull;
-    t.last = ((l >> 29) & 1) ? kLastCtl : 0ull;
-    if ((l >> 30) & 1)
-        t.last |= kLastHas | (((l >> 25) & 0xfull) << 56) | (u64)(tile_start + (int64_t)(l & 0x1ffffffull));
-    return t;
-}
-
-// Reads input bytes for conversion: from the LDS tile when inside it, from
-// HBM for the head of a field that began in an earlier tile.
-struct ByteSrc {
-    const uint8_t* lds;
-    const uint8_t* g;
-    int64_t tile_start;
-    int tile_size;  // bytes of the LDS tile buffer (a multiple of 4)
-    __device__ uint32_t operator()(int64_t pos) const
-    {
-        int64_t r = pos - tile_start;
-        return r >= 0 ? lds[r] : g[pos];
-    }
-};
-
-__device__ inline int64_t wave_sum(int64_t v)
-{
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
-}
-
-// Strip the enclosing control symbols of field [b, e) and convert it into
-// column c, record rec. ctl_first/ctl_last_sym: whether bytes b and e-1 are
-// control symbols. Returns 1 on a conversion error.
-__device__ inline int store_field(const Params& p, const ColDesc* cols, const ByteSrc& src, int c, int ty,
-                                  int64_t rec, int64_t b, int64_t e, bool ctl_first, bool ctl_last_sym)
-{
-    int64_t begin = b, end = e;
-    if (end > begin && ctl_first) ++begin;
-    if (end - 1 >= begin && ctl_last_sym) --end;
-    const bool store = rec < p.cap_records;
-    const ColDesc cd = cols[c];
-    if (ty == PP_STRING) {
-        if (store) {
-            ((int64_t*)cd.values)[rec] = begin;
-            cd.str_end[rec] = end;
-            cd.valid[rec] = 1;
-        }
-        return 0;
-    }
-    if (end == begin) {  // empty: the column default, not an error (Sec. 4.3)
-        if (store) {
-            ((int64_t*)cd.values)[rec] = 0;
-            cd.valid[rec] = 0;
-        }
-        return 0;
-    }
-    bool ok;
-    u64 bits;
-    int r = -1;
-    const int64_t off = begin - src.tile_start;
-    const int len = (int)(end - begin);
-    if (off >= 0 && len <= kWin) {  // short field inside the tile: parse from registers
-        const uint32_t* words = reinterpret_cast<const uint32_t*>(src.lds);
-        if (ty == PP_FLOAT64 || ty == PP_INT64) {
-            const Win x = load_win(words, src.tile_size, (int)off + len - kWin);  // right-aligned
-            const bool neg = src.lds[off] == '-';
-            if (ty == PP_FLOAT64) {
-                double dv = 0.0;
-                r = win_float64(x, len, neg, &dv);
-                bits = __builtin_bit_cast(u64, dv);
-            } else {
-                int64_t iv = 0;
-                r = win_int64(x, len, neg, &iv);
-                bits = (u64)iv;
-            }
-        } else {
-            const Win x = load_win(words, src.tile_size, (int)off);
-            int64_t iv = 0;
-            if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
-            else r = win_date(x, len, &iv);
-            bits = (u64)iv;
-        }
-    }
-    if (r >= 0) {
-        ok = r == 1;
-        if (!ok) bits = 0ull;
-    } else if (ty == PP_FLOAT64) {
-        double dv = 0.0;
-        ok = conv_float64(src, begin, end, &dv);
-        bits = ok ? __builtin_bit_cast(u64, dv) : 0ull;
-    } else {
-        int64_t iv = 0;
-        if (ty == PP_INT64) ok = conv_int64(src, begin, end, &iv);
-        else if (ty == PP_TIMESTAMP_S) ok = conv_timestamp(src, begin, end, &iv);
-        else ok = conv_date(src, begin, end, &iv);
-        bits = ok ? (u64)iv : 0ull;
-    }
-    if (store) {
-        ((u64*)cd.values)[rec] = bits;
-        cd.valid[rec] = ok;
-    }
-    return !ok;
-}
-
-__device__ inline void store_missing(const Params& p, const ColDesc* cols, int c, int ty, int64_t rec)
-{
-    if (rec >= p.cap_records || ty == PP_SKIP) return;
-    const ColDesc cd = cols[c];
-    ((u64*)cd.values)[rec] = 0;  // 0 and 0.0 share the bit pattern
-    cd.valid[rec] = 0;
-    if (ty == PP_STRING) cd.str_end[rec] = 0;
-}
-
-// ---- the kernel ---------------------------------------------------------------
 template <int NT, int B, bool NS8>
 __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 {
-    static_assert(B == 16 || B == 32 || B == 64, "chunk bitmaps are one or two dwords");
-    using M = std::conditional_t<(B > 32), u64, uint32_t>;
-    constexpr int TILE = NT * B;
-    constexpr int NW = NT / 64;
-    constexpr int FCAP = TILE / 4;   // delimiters staged per tile
-    constexpr int RCAP = TILE / 16;  // records staged per tile
-    static_assert(TILE <= 32768, "u16 positions");
-
-    __shared__ uint32_t s_tnext[NS8 ? 512 : 256];  // byte -> next state of every state
-    __shared__ uint32_t s_tcomb[NS8 ? 512 : 256];  // byte -> per state (next*8 | tag<<6)
-    __shared__ __align__(16) uint8_t s_bytes[TILE + 32];  // +32: register windows read past the end
-    __shared__ uint16_t s_pos[FCAP];     // tile-relative delimiter positions
-    __shared__ uint16_t s_colid[FCAP];   // column of the field each delimiter closes
-    __shared__ uint16_t s_recend[RCAP];  // local field index of each record delimiter
-    __shared__ uint32_t s_ctl[TILE / 32];  // control-symbol bitmap of the tile
-    __shared__ uint8_t s_types[PP_MAX_COLUMNS];
-    __shared__ ColDesc s_cols[PP_MAX_COLUMNS];
-    __shared__ ColDesc s_cb[PP_MAX_COLUMNS];  // column outputs offset to this tile's first record
-    __shared__ uint32_t s_anyctl;
-    __shared__ SV<NS8> s_wsv[NW];
-    __shared__ Cnt s_wcnt[NW];
-    __shared__ uint32_t s_tile, s_s0, s_final, s_last_sa, s_ctl_last;
-    __shared__ int s_lasttid;
-    __shared__ u64 s_pref[4];
-    __shared__ u64 s_err, s_ragged;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-
-    if (tid == 0) {
-        s_tile = atomicAdd(p.counter, 1u);  // tiles in start order: predecessors are running
-        s_lasttid = -1;
-        s_anyctl = 0;
-        s_err = 0;
-        s_ragged = 0;
-    }
-    // per-byte transition rows, precomputed by parse_init from the group table
-    for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
-        s_tnext[k] = p.tables[k];
-        s_tcomb[k] = p.tables[512 + k];
-    }
-    for (int c = tid; c < p.ncols; c += NT) {
-        s_types[c] = p.types[c];
-        s_cols[c] = p.cols[c];
-    }
+    __shared__ TileSmem<NT, B> sm;
+    __shared__ uint32_t s_ticket;
+    if (threadIdx.x == 0) s_ticket = atomicAdd(p.counter, 1u);
     __syncthreads();
-
-    const uint32_t tile = s_tile;
-    const int64_t n = p.n;
-    const int64_t tile_start = (int64_t)tile * TILE;
-    const int tile_len = (int)(n - tile_start < TILE ? n - tile_start : TILE);
-    u64* const tw = p.words + (size_t)tile * kWordsPerTile;
-
-    // ---- 1. stage the tile --------------------------------------------------------
-    {
-        const uint8_t* src = p.in + tile_start;
-        if (tile_len == TILE && (((uintptr_t)src) & 15) == 0) {
-            const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
-            u32x4* d4 = reinterpret_cast<u32x4*>(s_bytes);
-#pragma unroll
-            for (int k = tid; k < TILE / 16; k += NT) d4[k] = __builtin_nontemporal_load(s4 + k);
-        } else {
-            for (int k = tid; k < TILE; k += NT) s_bytes[k] = k < tile_len ? src[k] : 0;
-        }
-    }
-    __syncthreads();
-
-    const int c0 = tid * B;  // tile-relative chunk start
-    const int len = tile_len - c0 <= 0 ? 0 : (tile_len - c0 < B ? tile_len - c0 : B);
-    uint32_t wd[B / 4];
-    {
-        const uint4* q = reinterpret_cast<const uint4*>(s_bytes + c0);
-#pragma unroll
-        for (int k = 0; k < B / 16; ++k) {
-            uint4 v = q[k];
-            wd[4 * k] = v.x; wd[4 * k + 1] = v.y; wd[4 * k + 2] = v.z; wd[4 * k + 3] = v.w;
-        }
-    }
-    auto byte_at = [&](int i) -> uint32_t { return (wd[i >> 2] >> ((i & 3) * 8)) & 0xffu; };
-
-    // ---- 2. multi-state pass ----------------------------------------------------------
-    SV<NS8> vec = sv_identity<NS8>();
-    auto mstep = [&](int i) {
-        const uint32_t b = byte_at(i);
-        SV<NS8> t;
-        if constexpr (NS8) { t.lo = s_tnext[2 * b]; t.hi = s_tnext[2 * b + 1]; }
-        else { t.lo = s_tnext[b]; t.hi = 0; }
-        vec = compose(vec, t);
-    };
-    if (len == B) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) mstep(i);
-    } else {
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-            if (i < len) mstep(i);
-    }
-
-    // ---- 3. composition scan ------------------------------------------------------------
-    SV<NS8> incl = vec;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        SV<NS8> y = shfl_up_sv(incl, d);
-        if (lane >= d) incl = compose(y, incl);
-    }
-    if (lane == 63) s_wsv[wave] = incl;
-    __syncthreads();
-    SV<NS8> wpre = sv_identity<NS8>();
-    for (int w = 0; w < wave; ++w) wpre = compose(wpre, s_wsv[w]);
-    SV<NS8> ex = shfl_up_sv(incl, 1);
-    if (lane == 0) ex = sv_identity<NS8>();
-    ex = compose(wpre, ex);  // exclusive prefix of this chunk within the tile
-
-    if (wave == 0) {
-        SV<NS8> agg = sv_identity<NS8>();
-        for (int w = 0; w < NW; ++w) agg = compose(agg, s_wsv[w]);
-        SV<NS8> pre = sv_identity<NS8>();
-        if (tile == 0) {
-            if (lane == 0) publish(tw + W_STATE, kIncl | sv_to_nib(agg));
-        } else {
-            if (lane == 0) publish(tw + W_STATE, kAgg | sv_to_nib(agg));
-            // one wavefront polls 64 predecessors per step
-            SV<NS8> acc = sv_identity<NS8>();
-            for (int64_t base = (int64_t)tile - 1;; base -= 64) {
-                const int64_t j = base - lane;
-                u64 v = j >= 0 ? peek(p.words + (size_t)j * kWordsPerTile + W_STATE) : kIncl;
-                int first;
-                for (;;) {
-                    const u64 inc = ballot((v >> 62) == 2);
-                    const u64 rdy = ballot((v >> 62) != 0);
-                    first = inc ? __ffsll((long long)inc) - 1 : 64;
-                    const u64 need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-                    if ((rdy & need) == need) break;
-                    __builtin_amdgcn_s_sleep(1);
-                    if ((v >> 62) == 0) v = peek(p.words + (size_t)j * kWordsPerTile + W_STATE);
-                }
-                // ordered reduction, earlier tiles (higher lanes) on the left
-                SV<NS8> x = lane <= first ? sv_from_nib<NS8>((uint32_t)v) : sv_identity<NS8>();
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    SV<NS8> y = shfl_down_sv(x, d);
-                    if ((lane & (2 * d - 1)) == 0) x = compose(y, x);
-                }
-                SV<NS8> w;
-                w.lo = __builtin_amdgcn_readfirstlane(x.lo);
-                w.hi = __builtin_amdgcn_readfirstlane(x.hi);
-                acc = compose(w, acc);
-                if (first < 64) break;
-            }
-            pre = acc;
-            if (lane == 0) publish(tw + W_STATE, kIncl | sv_to_nib(compose(acc, agg)));
-        }
-        if (lane == 0) {
-            s_s0 = sv_get(pre, (uint32_t)p.start_state);
-            s_final = sv_get(compose(pre, agg), (uint32_t)p.start_state);
-        }
-    }
-    __syncthreads();
-    const uint32_t s_start = sv_get(ex, s_s0);
-
-    // ---- 4. tag pass ----------------------------------------------------------------------
-    // x = tcomb[b] >> (8*state): bits 3-5 next state * 8, bit 6 tag bit 0, bit 7 tag bit 1.
-    M p0 = 0, p1 = 0;
-    uint32_t s8 = s_start * 8u;
-    auto tstep = [&](int i) {
-        const uint32_t b = byte_at(i);
-        uint32_t x;
-        if constexpr (NS8) {
-            const uint32_t e = s_tcomb[2 * b + (s8 >> 5)];
-            x = __builtin_amdgcn_ubfe(e, s8 & 31u, 8);
-        } else {
-            x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
-        }
-        s8 = x & 0x38u;
-        p0 |= (M)((x >> 6) & 1u) << i;
-        p1 |= (M)(x >> 7) << i;
-    };
-    if (len == B) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) tstep(i);
-    } else {
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-            if (i < len) tstep(i);
-    }
-    const uint32_t s_end = s8 >> 3;
-    const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
-    const int64_t cstart = tile_start + c0;
-    const bool holds_last = len > 0 && cstart + len == n;
-    const uint32_t vend = holds_last && !((rmask >> (len - 1)) & 1u);  // end of input closes a record
-
-    // first transition into the (absorbing) invalid state
-    if (p.invalid_state >= 0 && s_start != (uint32_t)p.invalid_state && s_end == (uint32_t)p.invalid_state) {
-        const uint32_t inv8 = (uint32_t)p.invalid_state * 8u;
-        uint32_t r8 = s_start * 8u;
-        int at = -1;
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            if (i < len && at < 0) {
-                r8 = step_state<NS8>(s_tcomb, byte_at(i), r8);
-                if (r8 == inv8) at = i;
-            }
-        }
-        p.result->first_invalid_offset = cstart + at;
-    }
-
-    auto popc = [](M m) -> uint32_t {
-        if constexpr (B > 32) return (uint32_t)__popcll(m);
-        else return (uint32_t)__popc(m);
-    };
-    auto msb = [](M m) -> int {
-        if constexpr (B > 32) return 63 - __clzll((long long)m);
-        else return 31 - __clz((int)m);
-    };
-    Cnt mine;
-    mine.nr = popc(rmask) + vend;
-    mine.nf = popc(dmask) + vend;
-    if (rmask | vend) {
-        uint32_t after = 0;
-        if (!vend) {
-            const int hb = msb(rmask);
-            after = hb == B - 1 ? 0u : popc(dmask & ~rmask & (~(M)0 << (hb + 1)));
-        }
-        mine.col = kCAbs | after;
-    } else {
-        mine.col = popc(dmask);
-    }
-    mine.last = vend ? (uint32_t)(tile_len + 1) : (dmask ? (uint32_t)(c0 + msb(dmask) + 1) : 0u);
-    if (cmask) s_anyctl = 1u;
-    if constexpr (B == 64) {
-        s_ctl[2 * tid] = (uint32_t)cmask;
-        s_ctl[2 * tid + 1] = (uint32_t)(cmask >> 32);
-    } else if constexpr (B == 32) {
-        s_ctl[tid] = cmask;
-    } else {  // two 16-byte chunks per bitmap word
-        const uint32_t part = cmask << ((tid & 1) * 16);
-        const uint32_t other = (uint32_t)__shfl_xor((int)part, 1);
-        if ((tid & 1) == 0) s_ctl[tid >> 1] = part | other;
-    }
-
-    // ---- 5. count scans ------------------------------------------------------------------
-    Cnt cin = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        Cnt y = shfl_up_cnt(cin, d);
-        if (lane >= d) cin = cnt_combine(y, cin);
-    }
-    if (lane == 63) s_wcnt[wave] = cin;
-    if (mine.nf) atomicMax(&s_lasttid, tid);
-    __syncthreads();
-    Cnt cpre = {0u, 0u, 0u, 0u};
-    for (int w = 0; w < wave; ++w) cpre = cnt_combine(cpre, s_wcnt[w]);
-    Cnt cex = shfl_up_cnt(cin, 1);
-    if (lane == 0) cex = {0u, 0u, 0u, 0u};
-    cex = cnt_combine(cpre, cex);
-    Cnt tagg = {0u, 0u, 0u, 0u};
-    for (int w = 0; w < NW; ++w) tagg = cnt_combine(tagg, s_wcnt[w]);
-
-    // state after the tile's last delimiter, from the chunk that holds it
-    if (tid == s_lasttid) {
-        uint32_t sa = 0;
-        if (!vend) {
-            const int hb = msb(dmask);
-            uint32_t r8 = s_start * 8u;
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-                if (i <= hb) r8 = step_state<NS8>(s_tcomb, byte_at(i), r8);
-            sa = r8 >> 3;
-        }
-        s_last_sa = sa;
-    }
-    if (len > 0 && c0 + len == tile_len) s_ctl_last = (uint32_t)((cmask >> (len - 1)) & 1u);
-    __syncthreads();
-
-    if (wave == 0) {
-        // this tile's aggregate, in the device representation
-        const uint32_t lastrel = tagg.last;  // position + 1, 0 = none
-        const u64 a0 = ((u64)tagg.nr << 31) | tagg.nf;
-        const u64 colw = (tagg.col & kCAbs) ? ((1ull << 30) | (tagg.col & ~kCAbs)) : tagg.col;
-        u64 lastw = s_ctl_last ? (1ull << 29) : 0ull;
-        if (lastrel) lastw |= (1ull << 30) | ((u64)s_last_sa << 25) | (u64)(lastrel - 1);
-        const u64 a1 = (colw << 31) | lastw;
-        const Tot mineT = tot_from_agg(a0, a1, tile_start);
-        Tot pre = {0ull, 0ull, kColAbs, 0ull};  // seed: record 0, field 0, column (abs, 0)
-        if (tile > 0) {
-            if (lane == 0) {
-                publish(tw + W_AGG0, kAgg | a0);
-                publish(tw + W_AGG1, kAgg | a1);
-            }
-            bool have = false;
-            Tot acc;
-            for (int64_t base = (int64_t)tile - 1;; base -= 64) {
-                const int64_t j = base - lane;
-                u64* pw = p.words + (size_t)(j >= 0 ? j : 0) * kWordsPerTile;
-                u64 ir = 0, iF = 0, ic = 0, il = 0, g0 = 0, g1 = 0;
-                bool incl_ok = false, agg_ok = false;
-                int first;
-                for (;;) {
-                    if (j >= 0 && !incl_ok) {
-                        ir = peek(pw + W_IREC); iF = peek(pw + W_IFLD);
-                        ic = peek(pw + W_ICOL); il = peek(pw + W_ILAST);
-                        incl_ok = (ir >> 62) && (iF >> 62) && (ic >> 62) && (il >> 62);
-                        if (!incl_ok && !agg_ok) {
-                            g0 = peek(pw + W_AGG0); g1 = peek(pw + W_AGG1);
-                            agg_ok = (g0 >> 62) && (g1 >> 62);
-                        }
-                    }
-                    if (j < 0) incl_ok = true;  // before tile 0: the seed (never reached)
-                    const u64 inc = ballot(incl_ok);
-                    const u64 rdy = ballot(incl_ok || agg_ok);
-                    first = inc ? __ffsll((long long)inc) - 1 : 64;
-                    const u64 need = first >= 63 ? ~0ull : ((2ull << first) - 1);
-                    if ((rdy & need) == need) break;
-                    __builtin_amdgcn_s_sleep(1);
-                }
-                Tot x;
-                if (lane > first) x = {0ull, 0ull, 0ull, 0ull};
-                else if (incl_ok) x = {ir & kPayload, iF & kPayload, ic & kPayload, il & kPayload};
-                else x = tot_from_agg(g0, g1, (int64_t)j * TILE);
-                if (j < 0) x = {0ull, 0ull, kColAbs, 0ull};
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    Tot y = shfl_down_tot(x, d);
-                    if ((lane & (2 * d - 1)) == 0) x = tot_combine(y, x);
-                }
-                Tot w = {readlane0_64(x.rec), readlane0_64(x.fld), readlane0_64(x.col), readlane0_64(x.last)};
-                acc = have ? tot_combine(w, acc) : w;
-                have = true;
-                if (first < 64) break;
-            }
-            pre = acc;
-        }
-        const Tot inc = tot_combine(pre, mineT);
-        if (lane == 0) {
-            publish(tw + W_IREC, kIncl | inc.rec);
-            publish(tw + W_IFLD, kIncl | inc.fld);
-            publish(tw + W_ICOL, kIncl | inc.col);
-            publish(tw + W_ILAST, kIncl | inc.last);
-            s_pref[0] = pre.rec;
-            s_pref[1] = pre.fld;
-            s_pref[2] = pre.col;
-            s_pref[3] = pre.last;
-        }
-    }
-    __syncthreads();
-
-    const int64_t R0 = (int64_t)s_pref[0];
-    const int64_t F0 = (int64_t)s_pref[1];
-    const int64_t C0 = (int64_t)(s_pref[2] & kColVal);  // always absolute: seeded with (abs, 0)
-    const u64 lastw = s_pref[3];
-    const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
-    const int ncols = p.ncols;
-    const ByteSrc src{s_bytes, p.in, tile_start, TILE};
-    const bool last_has = (lastw & kLastHas) != 0;
-    const int64_t last_pos = (int64_t)(lastw & kLastPos);
-    const uint32_t last_sa = (uint32_t)((lastw >> 56) & 0xf);
-    const bool prev_ctl = (lastw & kLastCtl) != 0;
-
-    // control bit of byte b (b may precede the tile only for the tile's first field)
-    auto ctl_at_begin = [&](int64_t b) -> bool {
-        if (b >= tile_start) {
-            const int r = (int)(b - tile_start);
-            return (s_ctl[r >> 5] >> (r & 31)) & 1u;
-        }
-        const uint32_t by = p.in[b];
-        const uint32_t s8 = last_sa * 8u;
-        uint32_t x;
-        if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (s8 >> 5)], s8 & 31u, 8);
-        else x = __builtin_amdgcn_ubfe(s_tcomb[by], s8, 8);
-        return (x >> 6) == kTagControl;
-    };
-    auto ctl_at_end = [&](int64_t e) -> bool {  // control bit of byte e-1
-        if (e - 1 >= tile_start) {
-            const int r = (int)(e - 1 - tile_start);
-            return (s_ctl[r >> 5] >> (r & 31)) & 1u;
-        }
-        return prev_ctl;
-    };
-
-    int64_t nerr = 0, nragged = 0;
-    if (Ft <= FCAP && Rt <= RCAP && C0 + Ft < 65536) {
-        // ---- 6. emit structure through LDS --------------------------------------------------
-        {
-            uint32_t L = cex.nf, lr = cex.nr;
-            uint32_t col = (cex.col & kCAbs) ? (cex.col & ~kCAbs) : (uint32_t)C0 + cex.col;
-#pragma unroll
-            for (int h = 0; h < (B > 32 ? 2 : 1); ++h) {
-                uint32_t m = (uint32_t)(dmask >> (32 * h));
-                const uint32_t rm = (uint32_t)(rmask >> (32 * h));
-                const uint32_t base = (uint32_t)c0 + 32u * h;
-                while (m) {
-                    const uint32_t i = (uint32_t)__builtin_ctz(m);
-                    m &= m - 1;
-                    const bool isr = (rm >> i) & 1u;
-                    s_pos[L] = (uint16_t)(base + i);
-                    s_colid[L] = (uint16_t)col;
-                    if (isr) s_recend[lr++] = (uint16_t)L;
-                    col = isr ? 0u : col + 1u;
-                    ++L;
-                }
-            }
-            if (vend) {
-                s_pos[L] = (uint16_t)tile_len;
-                s_colid[L] = (uint16_t)col;
-                s_recend[lr] = (uint16_t)L;
-            }
-        }
-        if (tid < ncols) {  // column outputs as seen from this tile's first record
-            ColDesc d = s_cols[tid];
-            d.values = (char*)d.values + R0 * 8;
-            d.valid = d.valid + R0;
-            d.str_end = d.str_end + R0;
-            s_cb[tid] = d;
-        }
-        __syncthreads();
-        {
-            const int64_t roomf = p.cap_fields - F0;
-            const int kf = roomf < Ft ? (int)(roomf < 0 ? 0 : roomf) : Ft;
-            int64_t* const fo = p.field_offsets + F0 + 1;
-            int32_t* const ci = p.column_ids + F0;
-            for (int k = tid; k < kf; k += NT) {
-                fo[k] = tile_start + 1 + s_pos[k];
-                ci[k] = s_colid[k];
-            }
-            const int64_t roomr = p.cap_records - R0;
-            const int kr = roomr < Rt ? (int)(roomr < 0 ? 0 : roomr) : Rt;
-            int64_t* const ro = p.record_offsets + R0 + 1;
-            for (int k = tid; k < kr; k += NT) ro[k] = F0 + 1 + s_recend[k];
-        }
-
-        // ---- 7. typed columns, column-major over (column, local record) ------------------
-        const uint32_t nrec = (uint32_t)Rt + 1u;  // records closed here plus the open one
-        const uint32_t items = nrec * (uint32_t)ncols;
-        const int64_t roomr = p.cap_records - R0;
-        const uint32_t lr_cap = roomr <= 0 ? 0u : (roomr > (int64_t)nrec ? nrec : (uint32_t)roomr);
-        const bool anyctl = s_anyctl != 0;
-        const uint32_t* const words = reinterpret_cast<const uint32_t*>(s_bytes);
-        const uint32_t dq = (uint32_t)NT / nrec, dr = (uint32_t)NT % nrec;
-        uint32_t c = (uint32_t)tid / nrec, lr = (uint32_t)tid % nrec;
-        for (uint32_t q = tid; q < items; q += NT) {
-            const uint32_t first = lr ? s_recend[lr - 1] + 1u : 0u;
-            const uint32_t end1 = lr < (uint32_t)Rt ? s_recend[lr] + 1u : (uint32_t)Ft;  // one past the last field
-            const uint32_t cf = lr ? 0u : (uint32_t)C0;
-            if (c == 0 && lr < (uint32_t)Rt && cf + end1 - first != (uint32_t)ncols) ++nragged;
-            const uint32_t ty = s_types[c];
-            if (c >= cf && ty != PP_SKIP) {
-                const uint32_t L = first + c - cf;
-                if (L >= end1) {
-                    if (lr < (uint32_t)Rt && lr < lr_cap) {  // missing column of a short record
-                        const ColDesc cd = s_cb[c];
-                        ((u64*)cd.values)[lr] = 0;
-                        cd.valid[lr] = 0;
-                        if (ty == PP_STRING) cd.str_end[lr] = 0;
-                    }
-                } else if (L == 0) {  // may begin in an earlier tile: general path
-                    const int64_t e = tile_start + s_pos[0];
-                    const int64_t bb = last_has ? last_pos + 1 : 0;
-                    const bool cfst = e > bb && ctl_at_begin(bb);
-                    const bool clst = e > bb && ctl_at_end(e);
-                    nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, bb, e, cfst, clst);
-                } else {
-                    int bb = s_pos[L - 1] + 1, ee = s_pos[L];
-                    if (anyctl && ee > bb) {  // strip enclosing control symbols
-                        if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
-                        if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
-                    }
-                    const ColDesc cd = s_cb[c];
-                    const bool st = lr < lr_cap;
-                    if (ty == PP_STRING) {
-                        if (st) {
-                            ((int64_t*)cd.values)[lr] = tile_start + bb;
-                            cd.str_end[lr] = tile_start + ee;
-                            cd.valid[lr] = 1;
-                        }
-                    } else if (ee == bb) {  // empty: the column default, not an error
-                        if (st) {
-                            ((u64*)cd.values)[lr] = 0;
-                            cd.valid[lr] = 0;
-                        }
-                    } else {
-                        const int len = ee - bb;
-                        int r = -1;
-                        u64 bits = 0;
-                        if (len <= kWin) {
-                            const Win x = load_win_padded(words, bb);
-                            if (ty == PP_FLOAT64) {
-                                double dv = 0.0;
-                                r = ser_float64(x, len, &dv);
-                                bits = __builtin_bit_cast(u64, dv);
-                            } else {
-                                int64_t iv = 0;
-                                if (ty == PP_INT64) r = ser_int64(x, len, &iv);
-                                else if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
-                                else r = win_date(x, len, &iv);
-                                bits = (u64)iv;
-                            }
-                        }
-                        if (r < 0) {
-                            const int64_t gb = tile_start + bb, ge = tile_start + ee;
-                            if (ty == PP_FLOAT64) {
-                                double dv = 0.0;
-                                r = conv_float64(src, gb, ge, &dv);
-                                bits = __builtin_bit_cast(u64, dv);
-                            } else {
-                                int64_t iv = 0;
-                                if (ty == PP_INT64) r = conv_int64(src, gb, ge, &iv);
-                                else if (ty == PP_TIMESTAMP_S) r = conv_timestamp(src, gb, ge, &iv);
-                                else r = conv_date(src, gb, ge, &iv);
-                                bits = (u64)iv;
-                            }
-                        }
-                        nerr += r == 0;
-                        if (st) {
-                            ((u64*)cd.values)[lr] = r ? bits : 0ull;
-                            cd.valid[lr] = (uint8_t)r;
-                        }
-                    }
-                }
-            }
-            lr += dr;
-            c += dq;
-            if (lr >= nrec) { lr -= nrec; ++c; }
-        }
-        if (ncols == 0 && tid == 0) nragged = Rt;
-    } else {
-        // ---- 6'/7'. per-thread path: each thread closes the fields whose delimiter it holds
-        uint32_t L = cex.nf;
-        int64_t lr = cex.nr;
-        int64_t col = (cex.col & kCAbs) ? (int64_t)(cex.col & ~kCAbs) : C0 + (int64_t)cex.col;
-        int64_t prev = cex.last ? tile_start + (int64_t)cex.last - 1 : (last_has ? last_pos : -1);
-        M m = dmask;
-        const int cnt = (int)popc(dmask) + (int)vend;
-        for (int k = 0; k < cnt; ++k) {
-            int64_t pos;
-            bool isrec;
-            if (m) {
-                const int i = B > 32 ? __ffsll((long long)m) - 1 : __ffs((int)m) - 1;
-                m &= m - 1;
-                pos = cstart + i;
-                isrec = (rmask >> i) & 1u;
-            } else {  // the virtual delimiter at the end of input
-                pos = n;
-                isrec = true;
-            }
-            const int64_t f = F0 + L;
-            if (f + 1 <= p.cap_fields) p.field_offsets[f + 1] = pos + 1;
-            if (f < p.cap_fields) p.column_ids[f] = (int32_t)col;
-            const int64_t rec = R0 + lr;
-            if (col < ncols) {
-                const int ty = s_types[col];
-                if (ty != PP_SKIP) {
-                    const int64_t b = prev + 1;
-                    const bool cfst = pos > b && ctl_at_begin(b);
-                    const bool clst = pos > b && ctl_at_end(pos);
-                    nerr += store_field(p, s_cols, src, (int)col, ty, rec, b, pos, cfst, clst);
-                }
-            }
-            if (isrec) {
-                if (col + 1 != ncols) ++nragged;
-                for (int64_t c = col + 1; c < ncols; ++c) store_missing(p, s_cols, (int)c, s_types[c], rec);
-                if (rec + 1 <= p.cap_records) p.record_offsets[rec + 1] = f + 1;
-                ++lr;
-                col = 0;
-            } else {
-                ++col;
-            }
-            prev = pos;
-            ++L;
-        }
-    }
-
-    nerr = wave_sum(nerr);
-    nragged = wave_sum(nragged);
-    if (lane == 0 && (nerr | nragged)) {
-        atomicAdd(&s_err, (u64)nerr);
-        atomicAdd(&s_ragged, (u64)nragged);
-    }
-    __syncthreads();
-    if (tid == 0) {
-        if (s_err) atomicAdd((u64*)&p.result->num_conversion_errors, s_err);
-        if (s_ragged) atomicAdd((u64*)&p.result->num_ragged_records, s_ragged);
-        if (tile == (uint32_t)p.num_tiles - 1) {
-            const int64_t R = R0 + Rt, F = F0 + Ft;
-            const uint32_t fin = s_final;
-            int64_t st;
-            if (R > p.cap_records || F > p.cap_fields) st = PP_RESULT_CAPACITY;
-            else if (p.invalid_state >= 0 && fin == (uint32_t)p.invalid_state) st = PP_RESULT_INVALID_INPUT;
-            else if (!((p.accept_mask >> fin) & 1u)) st = PP_RESULT_NON_ACCEPTING_END;
-            else st = PP_RESULT_OK;
-            p.result->num_records = R;
-            p.result->num_fields = F;
-            p.result->final_state = fin;
-            p.result->status = st;
-        }
-    }
+    parse_tile<NT, B, NS8>(p.a, s_ticket, sm);
 }
 
 // Resets the workspace and the result before a parse; writes the outputs of
@@ -977,7 +43,8 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 __global__ void parse_init(Params p, size_t nwords)
 {
     const size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-    for (size_t k = i; k < nwords; k += (size_t)gridDim.x * blockDim.x) p.words[k] = 0ull;
+    for (size_t k = i; k < nwords; k += (size_t)gridDim.x * blockDim.x) p.a.words[k] = 0ull;
+    if (i < (size_t)p.a.ncols) p.colws[i] = p.cols[i];
     if (i < 256) {
         // per-byte transition rows from the DFA's group table (Table 1 layout):
         // next state of every state, and (next*8 | tag<<6) of every state
@@ -985,14 +52,14 @@ __global__ void parse_init(Params p, size_t nwords)
         const uint32_t g = p.group_of[b];
         uint32_t lo = 0, hi = 0, clo = 0, chi = 0;
         for (int s = 0; s < 8; ++s) {
-            const bool real = s < p.num_states;
+            const bool real = s < p.a.num_states;
             const uint32_t nx = real ? p.next[g][s] : (uint32_t)s;
             const uint32_t tg = real ? p.tag[g][s] : 0u;
             const uint32_t cb = (nx * 8u) | (tg << 6);
             if (s < 4) { lo |= nx << (8 * s); clo |= cb << (8 * s); }
             else { hi |= nx << (8 * (s - 4)); chi |= cb << (8 * (s - 4)); }
         }
-        if (p.num_states > 4) {
+        if (p.a.num_states > 4) {
             p.tables[2 * b] = lo; p.tables[2 * b + 1] = hi;
             p.tables[512 + 2 * b] = clo; p.tables[512 + 2 * b + 1] = chi;
         } else {
@@ -1002,16 +69,16 @@ __global__ void parse_init(Params p, size_t nwords)
     }
     if (i == 0) {
         *p.counter = 0u;
-        pp_result_t* r = p.result;
+        pp_result_t* r = p.a.result;
         r->first_invalid_offset = -1;
         r->num_conversion_errors = 0;
         r->num_ragged_records = 0;
         r->num_records = 0;
         r->num_fields = 0;
-        r->final_state = p.start_state;
-        r->status = ((p.accept_mask >> p.start_state) & 1u) ? PP_RESULT_OK : PP_RESULT_NON_ACCEPTING_END;
-        if (p.record_offsets && p.cap_records >= 0) p.record_offsets[0] = 0;
-        if (p.field_offsets && p.cap_fields >= 0) p.field_offsets[0] = 0;
+        r->final_state = p.a.start_state;
+        r->status = ((p.a.accept_mask >> p.a.start_state) & 1u) ? PP_RESULT_OK : PP_RESULT_NON_ACCEPTING_END;
+        if (p.a.record_offsets && p.a.cap_records >= 0) p.a.record_offsets[0] = 0;
+        if (p.a.field_offsets && p.a.cap_fields >= 0) p.a.field_offsets[0] = 0;
     }
 }
 
@@ -1067,7 +134,7 @@ extern "C" size_t pp_workspace_size(int64_t n, const pp_options_t* opts)
     if (n < 0 || !shape_of(opts, &sh)) return 0;
     const int64_t tb = (int64_t)sh.nt * sh.b;
     const int64_t tiles = (n + tb - 1) / tb;
-    return kWsHeader + kWsTables + (size_t)tiles * kWordsPerTile * sizeof(u64);
+    return kWsHeader + kWsTables + kWsCols + (size_t)tiles * kWordsPerTile * sizeof(u64);
 }
 
 extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
@@ -1089,26 +156,31 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
 
     Params p;
     memset(&p, 0, sizeof p);
-    p.in = d_in;
-    p.n = n;
-    p.cap_records = out->cap_records;
-    p.cap_fields = out->cap_fields;
-    p.record_offsets = out->d_record_offsets;
-    p.field_offsets = out->d_field_offsets;
-    p.column_ids = out->d_column_ids;
-    p.result = out->d_result;
+    TileArgs& a = p.a;
+    a.in = d_in;
+    a.n = n;
+    a.cap_records = out->cap_records;
+    a.cap_fields = out->cap_fields;
+    a.record_offsets = out->d_record_offsets;
+    a.field_offsets = out->d_field_offsets;
+    a.column_ids = out->d_column_ids;
+    a.result = out->d_result;
     p.counter = (unsigned int*)d_ws;
     p.tables = (uint32_t*)((char*)d_ws + kWsHeader);
-    p.words = (u64*)((char*)d_ws + kWsHeader + kWsTables);
+    p.colws = (ColDesc*)((char*)d_ws + kWsHeader + kWsTables);
+    a.tables = p.tables;
+    a.cols = p.colws;
+    a.words = (u64*)((char*)d_ws + kWsHeader + kWsTables + kWsCols);
     const int64_t tb = (int64_t)sh.nt * sh.b;
     const int64_t tiles = (n + tb - 1) / tb;
-    if (tiles > 0x7fffffff) return PP_ERR_UNSUPPORTED;
-    p.num_tiles = (int32_t)tiles;
-    p.ncols = schema->ncols;
-    p.num_states = dfa->num_states;
-    p.start_state = dfa->start_state;
-    p.invalid_state = dfa->invalid_state;
-    p.accept_mask = dfa->accept_mask;
+    // the dispatch counts work-items in 32 bits
+    if (tiles * sh.nt > 0xffffffffll) return PP_ERR_UNSUPPORTED;
+    a.num_tiles = (int32_t)tiles;
+    a.ncols = schema->ncols;
+    a.num_states = dfa->num_states;
+    a.start_state = dfa->start_state;
+    a.invalid_state = dfa->invalid_state;
+    a.accept_mask = dfa->accept_mask;
     memcpy(p.group_of, dfa->group_of, 256);
     for (int g = 0; g < PP_MAX_GROUPS; ++g)
         for (int s = 0; s < PP_MAX_STATES; ++s) {
@@ -1119,7 +191,7 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     for (int c = 0; c < schema->ncols; ++c) {
         const int32_t ty = schema->types[c];
         if (ty < PP_INT64 || ty > PP_SKIP) return PP_ERR_SCHEMA;
-        p.types[c] = (uint8_t)ty;
+        p.cols[c].type = ty;
         if (ty == PP_SKIP) continue;
         if (out->cap_records > 0) {
             if (!out->d_values || !out->d_valid || !out->d_values[c] || !out->d_valid[c]) return PP_ERR_ARG;
@@ -1155,6 +227,7 @@ extern "C" const char* pp_status_str(pp_status_t s)
     case PP_ERR_WORKSPACE: return "workspace too small";
     case PP_ERR_HIP: return "HIP launch failed";
     case PP_ERR_UNSUPPORTED: return "unsupported";
+    case PP_ERR_BUDGET: return "larger than the device budget";
     }
     return "unknown status";
 }

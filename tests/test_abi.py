@@ -38,6 +38,7 @@ def test_no_oracle_in_product_library():
 
 def test_workspace_size_and_status_text():
     head = 256 + 4096  # ticket counter, byte tables
+    head += 64 * 32  # column descriptors
     assert pp.workspace_size(0) == head
     assert pp.workspace_size(32768) == head + 8 * 8          # default: 512 threads x 64 B
     assert pp.workspace_size(32769) == head + 2 * 8 * 8
