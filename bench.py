@@ -25,6 +25,34 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+KERNEL_SOURCES = ["paper_1905_13415_amd/csrc/tile.h", "paper_1905_13415_amd/csrc/parse.hip",
+                  "paper_1905_13415_amd/csrc/convert.h", "paper_1905_13415_amd/csrc/convert_fast.h"]
+TRAFFIC_FILE = "profiles/parse_tiles_c2_1GiB_traffic.json"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per launch of the dominant kernel from the committed
+    counter runs (FETCH_SIZE, WRITE_SIZE, each scaled by a plain copy's
+    reading), or None when the kernel sources changed since they were taken."""
+    try:
+        with open(os.path.join(ROOT, TRAFFIC_FILE)) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("source_sha256") != kernel_source_hash():
+        return None
+    return t["fetch_bytes"] + t["write_bytes"]
+
+
 def output_bytes(R, F, types):
     """Algorithmic output bytes: what the method must write."""
     b = (R + 1) * 8 + (F + 1) * 8 + F * 4
@@ -47,9 +75,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many launches (for rocprofv3), no JSON")
-    ap.add_argument("--workload", choices=["c2", "c4"], default="c2",
+    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
                     help="c2: 1 GiB numeric CSV, plain launch (default); "
-                         "c4: 4,096 mixed-dialect buffers, batched launch against plain launches")
+                         "c4: 4,096 mixed-dialect buffers, batched launch against plain launches; "
+                         "c5: request loop over pinned host inputs, p50/p99 latency")
+    ap.add_argument("--c5-requests", type=int, default=2000)
+    ap.add_argument("--c5-pool-bytes", type=int, default=1 << 30,
+                    help="size of the pinned log text that c5 requests are cut from")
+    ap.add_argument("--c5-budget", type=int, default=32 << 30, help="server device budget, bytes")
     ap.add_argument("--c4-max-bytes", type=int, default=64 << 20,
                     help="upper bound of the c4 buffer sizes (8 MiB gives the ~4 GB variant)")
     args = ap.parse_args()
@@ -60,6 +93,8 @@ def main():
         sys.exit(2)
     if args.workload == "c4":
         return bench_c4(args)
+    if args.workload == "c5":
+        return bench_c5(args)
 
     import numpy as np
     import torch
@@ -170,7 +205,7 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(inout_gbs / HBM_PEAK_GBS, 4),
-            "traffic": None,
+            "traffic": measured_traffic() if args.nbytes == 1 << 30 and not args.bytes_per_thread else None,
         },
     }
 
@@ -240,7 +275,12 @@ def bench_c4(args):
                 print(f"[bench] {tag}: buffer {i} unexpected result {res[i].tolist()}", file=sys.stderr)
                 sys.exit(1)
 
-    batch = pp.Batch(dfas, items)
+    # launch shape (bytes per thread, block threads) from the autotuner
+    t0 = time.time()
+    best, tune = pp.autotune_batch(dfas, items, reps=2)
+    print(f"[bench] autotuned shape {best.block_threads}x{best.bytes_per_thread} in {time.time() - t0:.1f}s "
+          f"({tune['ms']} ms per shape)", file=sys.stderr, flush=True)
+    batch = pp.Batch(dfas, items, opts=best)
     batch.capture()
     if args.profile_steps:
         for _ in range(args.profile_steps):
@@ -296,6 +336,22 @@ def bench_c4(args):
             sys.exit(1)
     p_steps = max(3, min(args.steps, 10))
     p_per, p_host = timed(plain_pass, p_steps)
+    # the plain launches without the host's pace: queue them all behind a
+    # spin kernel longer than their enqueue, time from the end of the spin
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    torch.cuda._sleep(1_000_000)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    ticks_per_ms = 1_000_000 / c0.elapsed_time(c1)
+    torch.cuda._sleep(int(ticks_per_ms * (1.5 * p_host + 50)))
+    c0.record(stream)
+    h0 = time.perf_counter()
+    plain_pass()
+    enq_ms = (time.perf_counter() - h0) * 1e3
+    c1.record(stream)
+    torch.cuda.synchronize()
+    p_queued = c0.elapsed_time(c1)
 
     b_ms = sum(b_per) / len(b_per)
     p_ms = sum(p_per) / len(p_per)
@@ -318,14 +374,19 @@ def bench_c4(args):
             "workload": f"c4: {len(items)} buffers, sizes log-uniform in [1 KiB, {args.c4_max_bytes >> 20} MiB], "
                         "18 dialects (3- to 8-state DFAs x comma/tab/pipe), one captured batched launch",
             "bytes": total, "buffers": len(items), "work_items": batch.num_tiles,
+            "block_threads": best.block_threads, "bytes_per_thread": best.bytes_per_thread,
         },
+        "autotune_ms_per_shape": {f"{o.block_threads}x{o.bytes_per_thread}": m
+                                  for o, m in zip(pp.shapes(), tune["ms"])},
         "batched_ms": {"mean": round(b_ms, 4), "median": round(b_per[len(b_per) // 2], 4),
                        "min": round(b_per[0], 4), "max": round(b_per[-1], 4), "host_enqueue_ms": round(b_host, 4)},
         "plain_ms": {"mean": round(p_ms, 4), "median": round(p_per[len(p_per) // 2], 4),
                      "min": round(p_per[0], 4), "max": round(p_per[-1], 4), "host_enqueue_ms": round(p_host, 4),
-                     "launches": 2 * len(calls)},
+                     "launches": 2 * len(calls),
+                     "prequeued_ms": round(p_queued, 4), "prequeued_enqueue_ms": round(enq_ms, 4)},
         "plain_gbs": round(total / (p_ms / 1e3) / 1e9, 2),
         "batched_speedup_vs_plain": round(p_ms / b_ms, 3),
+        "batched_speedup_vs_prequeued_plain": round(p_queued / b_ms, 3),
         "input_gbs": round(in_gbs, 2),
         "in_out_gbs": round(inout_gbs, 2),
         "output_bytes": outb,
@@ -368,6 +429,131 @@ def bench_c4(args):
                                 "pool": {"value": round(acc / cpun / 1e9, 4), "cores": cores,
                                          "note": "same sample, one buffer per task"}}
     batch.close()
+    print(json.dumps(line), flush=True)
+
+
+def bench_c5(args):
+    """Serving: requests cut at record boundaries from a pinned extended-log
+    text (6-state DFA, 12 columns), sizes log-uniform in [4 KiB, 256 MiB],
+    Poisson arrivals at offered loads of 0.5, 0.8 and 1.0 times the serial
+    capacity, served by the request loop (continuous batching, copies
+    overlapped with parsing) and, on the same trace, by the loop restricted to
+    one request at a time (copy, then parse, no overlap). Latency is arrival
+    to the end of the request's parse on the device."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1905_13415_amd as pp
+    from datagen import dialects as D
+
+    dfa = D.log6()
+    types = list(D.SCHEMA_LOG12.types)
+    t0 = time.time()
+    g = datagen.log(datagen.SEED_BASE + 4, args.c5_pool_bytes)
+    data = g.data
+    ends = np.flatnonzero(data == 10) + 1  # no LF inside a log record: every LF ends one
+    starts = np.concatenate([[0], ends[:-1]])
+    pool = torch.empty(len(data), dtype=torch.uint8).pin_memory()
+    pool.numpy()[:] = data
+    rng = np.random.default_rng(datagen.SEED_BASE + 4)
+    N = args.c5_requests
+    sizes = np.exp(rng.uniform(np.log(4096), np.log(256 << 20), size=N)).astype(np.int64)
+    reqs = []
+    for sz in sizes:
+        last_ok = int(np.searchsorted(starts, len(data) - sz, side="right")) - 1
+        i = int(rng.integers(0, max(last_ok, 0) + 1))
+        j = int(np.searchsorted(ends, starts[i] + sz, side="left"))
+        j = min(j, len(ends) - 1)
+        a, b = int(starts[i]), int(ends[j])
+        reqs.append((pool[a:b], j - i + 1))
+    total = sum(int(r[0].numel()) for r in reqs)
+    print(f"[bench] pool {len(data)} bytes, {N} requests, {total} bytes in {time.time() - t0:.1f}s",
+          file=sys.stderr, flush=True)
+
+    # pinned host -> device copy rate, the bound of this form
+    dev = torch.device("cuda:0")
+    dst = torch.empty(256 << 20, dtype=torch.uint8, device=dev)
+    dst.copy_(pool[:256 << 20], non_blocking=True)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(4):
+        dst.copy_(pool[:256 << 20], non_blocking=True)
+    e1.record()
+    torch.cuda.synchronize()
+    h2d_gbs = 4 * (256 << 20) / (e0.elapsed_time(e1) / 1e3) / 1e9
+    del dst
+
+    def run(arrivals_ns, serial):
+        if serial:
+            srv = pp.Server([dfa], args.c5_budget, max_slots=1, copy_streams=1, compute_streams=1)
+        else:
+            srv = pp.Server([dfa], args.c5_budget, max_slots=256, copy_streams=2, compute_streams=2)
+        lat, first, last = [], None, 0
+        i = done = 0
+        base = time.monotonic_ns() + 2_000_000
+        while done < N:
+            now = time.monotonic_ns()
+            while i < N and base + arrivals_ns[i] <= now:
+                t, R = reqs[i]
+                srv.submit(t, 0, types, R, 12 * R)
+                i += 1
+            for c in srv.poll():
+                if c.result["status"] != pp.RESULT_OK:
+                    print(f"[bench] request {c.id}: {c.result}", file=sys.stderr)
+                    sys.exit(1)
+                lat.append(c.latency_ns)
+                first = c.t_arrival_ns if first is None else min(first, c.t_arrival_ns)
+                last = max(last, c.t_parse_done_ns)
+                srv.release(c.id)
+                done += 1
+            if i >= N:
+                srv.wait(500)
+        st = srv.stats()
+        srv.close()
+        lat = np.sort(np.array(lat)) / 1e6
+        return {"p50_ms": round(float(np.percentile(lat, 50)), 3),
+                "p99_ms": round(float(np.percentile(lat, 99)), 3),
+                "mean_ms": round(float(lat.mean()), 3),
+                "sustained_gbs": round(total / ((last - first) / 1e9) / 1e9, 2),
+                "batches": st["batches"], "max_batch": st["max_batch"]}
+
+    zero = np.zeros(N, dtype=np.int64)
+    closed_serial = run(zero, True)  # everything queued at once, one at a time
+    service_ns = (total / (closed_serial["sustained_gbs"] * 1e9)) * 1e9 / N
+    closed = run(zero, False)
+    loads = {}
+    for rho in (0.5, 0.8, 1.0):
+        gaps = rng.exponential(service_ns / rho, size=N)
+        arr = np.cumsum(gaps).astype(np.int64) - int(gaps[0])
+        loads[str(rho)] = {"overlapped": run(arr, False), "serial": run(arr, True)}
+        print(f"[bench] load {rho}: {loads[str(rho)]}", file=sys.stderr, flush=True)
+    line = {
+        "metric": "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency",
+        "value": closed["sustained_gbs"],
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": N,
+        "warmup": 0,
+        "ms_per_step": round(total / (closed["sustained_gbs"] * 1e9) * 1e3 / N, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded extended-log text; no dataset used)",
+        "config": {
+            "workload": f"c5: {N} requests cut from a {len(data)}-byte pinned log text, sizes log-uniform in "
+                        "[4 KiB, 256 MiB], log6 DFA, 12 columns, request loop with continuous batching",
+            "bytes": total, "budget_bytes": args.c5_budget,
+        },
+        "saturated": {"overlapped": closed, "serial": closed_serial},
+        "serial_service_ms": round(service_ns / 1e6, 4),
+        "poisson": loads,
+        "pcie_h2d_gbs": round(h2d_gbs, 2),
+        "roofline": {"bound": "pcie", "achieved": closed["sustained_gbs"], "peak": round(h2d_gbs, 2),
+                     "unit": "GB/s", "frac": round(closed["sustained_gbs"] / h2d_gbs, 4), "traffic": None},
+    }
     print(json.dumps(line), flush=True)
 
 

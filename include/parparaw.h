@@ -194,6 +194,30 @@ pp_status_t pp_batch_graph_launch(pp_batch_graph_t* graph, void* stream);
 void pp_batch_graph_destroy(pp_batch_graph_t* graph);
 void pp_batch_destroy(pp_batch_t* batch);
 
+/* ---- launch-shape autotuner -------------------------------------------------
+ * The launch shape fixes the chunk of Sec. 3.1 (bytes per thread) and the
+ * scan tile (threads x bytes). These calls time every supported shape on the
+ * caller's own inputs and outputs with HIP events (one untimed launch, then
+ * reps timed ones per shape), synchronise the host on `stream`, and return
+ * the fastest shape in *best; ms (optional, PP_NUM_SHAPES floats) receives
+ * each shape's mean milliseconds, -1 for shapes skipped because the
+ * workspace is too small for them. Outputs are overwritten with the results
+ * of the last shape timed (identical for every shape). */
+#define PP_NUM_SHAPES 5
+/* The i-th supported shape, 0 <= i < PP_NUM_SHAPES. */
+pp_status_t pp_shape(int32_t i, pp_options_t* out);
+/* A workspace size that serves pp_parse of n bytes under every shape. */
+size_t pp_autotune_workspace_size(int64_t n);
+pp_status_t pp_parse_autotune(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, const pp_schema_t* schema,
+                              const pp_outputs_t* out, void* d_ws, size_t ws_bytes, int32_t reps, void* stream,
+                              pp_options_t* best, float* ms);
+/* A workspace size that serves the batch under every shape. */
+size_t pp_batch_autotune_workspace_size(const pp_dfa_t* dfas, int32_t ndfas, const pp_batch_item_t* items,
+                                        int32_t count);
+pp_status_t pp_batch_autotune(const pp_dfa_t* dfas, int32_t ndfas, const pp_batch_item_t* items, int32_t count,
+                              void* d_ws, size_t ws_bytes, int32_t reps, void* stream, pp_options_t* best,
+                              float* ms);
+
 /* ---- serving form ---------------------------------------------------------
  * A request loop in front of the batched form, for host-resident inputs: the
  * streaming setting of Sec. 4.4 (transfers overlapped with parsing) with

@@ -16,11 +16,13 @@ from typing import List, Optional, Sequence
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
-SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip")]
 
 PP_OK = 0
 STATUS_TEXT = {0: "ok", -1: "invalid argument", -2: "invalid DFA", -3: "invalid schema",
-               -4: "workspace too small", -5: "HIP launch failed", -6: "unsupported"}
+               -4: "workspace too small", -5: "HIP launch failed", -6: "unsupported",
+               -7: "larger than the device budget"}
+PP_ERR_BUDGET = -7
 INT64, FLOAT64, TIMESTAMP_S, DATE_DAYS, STRING, SKIP = 0, 1, 2, 3, 4, 5
 RESULT_OK, RESULT_INVALID_INPUT, RESULT_NON_ACCEPTING_END, RESULT_CAPACITY = 0, 1, 2, 3
 MAX_COLUMNS = 64
@@ -104,6 +106,31 @@ def lib():
         L.pp_batch_graph_destroy.argtypes = [P]
         L.pp_batch_destroy.restype = None
         L.pp_batch_destroy.argtypes = [P]
+        L.pp_shape.restype = ctypes.c_int32
+        L.pp_shape.argtypes = [ctypes.c_int32, P]
+        L.pp_autotune_workspace_size.restype = ctypes.c_size_t
+        L.pp_autotune_workspace_size.argtypes = [ctypes.c_int64]
+        L.pp_parse_autotune.restype = ctypes.c_int32
+        L.pp_parse_autotune.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, ctypes.c_int32, P, P, P]
+        L.pp_batch_autotune_workspace_size.restype = ctypes.c_size_t
+        L.pp_batch_autotune_workspace_size.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32]
+        L.pp_batch_autotune.restype = ctypes.c_int32
+        L.pp_batch_autotune.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_size_t, ctypes.c_int32,
+                                        P, P, P]
+        L.pp_server_create.restype = ctypes.c_int32
+        L.pp_server_create.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(P)]
+        L.pp_server_submit.restype = ctypes.c_int32
+        L.pp_server_submit.argtypes = [P, P, ctypes.POINTER(ctypes.c_uint64)]
+        L.pp_server_poll.restype = ctypes.c_int32
+        L.pp_server_poll.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(ctypes.c_int32)]
+        L.pp_server_wait.restype = ctypes.c_int32
+        L.pp_server_wait.argtypes = [P, ctypes.c_int64]
+        L.pp_server_release.restype = ctypes.c_int32
+        L.pp_server_release.argtypes = [P, ctypes.c_uint64]
+        L.pp_server_get_stats.restype = ctypes.c_int32
+        L.pp_server_get_stats.argtypes = [P, P]
+        L.pp_server_destroy.restype = None
+        L.pp_server_destroy.argtypes = [P]
         _lib = L
     return _lib
 
@@ -239,6 +266,31 @@ def _check(rc, what):
         raise PpError(f"{what}: {STATUS_TEXT.get(rc, rc)}")
 
 
+def _batch_items(items):
+    """Marshal (d_in, dialect index, types, Outputs) tuples into a
+    pp_batch_item_t array; returns it with the ctypes objects it points to."""
+    keep = []
+    arr = (PpBatchItem * max(len(items), 1))()
+    for i, (d_in, dialect, types, out) in enumerate(items):
+        n = int(d_in.numel())
+        nc = len(types)
+        t = (ctypes.c_int32 * max(nc, 1))(*types)
+        vp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.values])
+        mp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.valid])
+        ep = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.str_end])
+        keep += [t, vp, mp, ep]
+        arr[i].d_in = d_in.data_ptr() if n else None
+        arr[i].n = n
+        arr[i].dialect = dialect
+        arr[i].ncols = nc
+        arr[i].types = ctypes.cast(t, ctypes.c_void_p)
+        arr[i].out = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets),
+                               _ptr(out.field_offsets), _ptr(out.column_ids),
+                               ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
+                               ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result))
+    return arr, keep
+
+
 class Batch:
     """Many buffers with their own dialects and outputs in one
     launch (pp_batch_*). ``items`` is a list of (d_in, dialect index, types,
@@ -248,25 +300,8 @@ class Batch:
         import torch
         L = lib()
         self._dfas = (PpDfa * len(dfas))(*[dfa_struct(d) for d in dfas])
-        self._keep = []
-        arr = (PpBatchItem * max(len(items), 1))()
-        for i, (d_in, dialect, types, out) in enumerate(items):
-            n = int(d_in.numel())
-            nc = len(types)
-            t = (ctypes.c_int32 * max(nc, 1))(*types)
-            vp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.values])
-            mp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.valid])
-            ep = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.str_end])
-            self._keep += [t, vp, mp, ep]
-            arr[i].d_in = d_in.data_ptr() if n else None
-            arr[i].n = n
-            arr[i].dialect = dialect
-            arr[i].ncols = nc
-            arr[i].types = ctypes.cast(t, ctypes.c_void_p)
-            arr[i].out = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets),
-                                   _ptr(out.field_offsets), _ptr(out.column_ids),
-                                   ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
-                                   ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result))
+        arr, self._keep = _batch_items(items)
+        self.opts = opts
         self.items = items
         h = ctypes.c_void_p()
         _check(L.pp_batch_create(self._dfas, len(dfas), arr, len(items),
@@ -313,3 +348,284 @@ class Batch:
             self.close()
         except Exception:
             pass
+
+
+# ---- serving form ------------------------------------------------------------
+
+class PpServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("copy_streams", ctypes.c_int32), ("compute_streams", ctypes.c_int32),
+                ("max_batch", ctypes.c_int32), ("opts", PpOptions)]
+
+
+class PpServerRequest(ctypes.Structure):
+    _fields_ = [("h_in", ctypes.c_void_p), ("n", ctypes.c_int64), ("dialect", ctypes.c_int32),
+                ("ncols", ctypes.c_int32), ("types", ctypes.c_void_p), ("cap_records", ctypes.c_int64),
+                ("cap_fields", ctypes.c_int64)]
+
+
+class PpResult(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in RESULT_FIELDS]
+
+
+class PpServerCompletion(ctypes.Structure):
+    _fields_ = [("id", ctypes.c_uint64), ("n", ctypes.c_int64), ("result", PpResult), ("out", PpOutputs),
+                ("t_arrival_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_h2d_done_ns", ctypes.c_int64), ("t_parse_done_ns", ctypes.c_int64)]
+
+
+class PpServerStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in
+                ("submitted", "completed", "reparsed", "batches", "batched_requests", "max_batch",
+                 "bytes_completed", "arena_bytes", "arena_used_bytes", "arena_peak_bytes", "pending",
+                 "hip_error")]
+
+
+_hip = None
+
+
+def _hip_lib():
+    """The HIP runtime torch has loaded (for reading server outputs)."""
+    global _hip
+    if _hip is None:
+        import torch  # noqa: F401  (loads the runtime)
+        h = ctypes.CDLL("libamdhip64.so")
+        h.hipMemcpy.restype = ctypes.c_int
+        h.hipMemcpy.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int]
+        _hip = h
+    return _hip
+
+
+def device_to_numpy(ptr: int, count: int, dtype):
+    """Synchronous copy of ``count`` elements at device address ``ptr``."""
+    import numpy as np
+    a = np.empty(count, dtype=dtype)
+    if count:
+        rc = _hip_lib().hipMemcpy(a.ctypes.data, ptr, a.nbytes, 2)  # device to host
+        if rc != 0:
+            raise PpError(f"hipMemcpy failed ({rc})")
+    return a
+
+
+@dataclass
+class Completion:
+    id: int
+    n: int
+    result: dict
+    t_arrival_ns: int
+    t_admit_ns: int
+    t_h2d_done_ns: int
+    t_parse_done_ns: int
+    _out: "PpServerCompletion"
+    types: List[int]
+
+    @property
+    def latency_ns(self) -> int:
+        return self.t_parse_done_ns - self.t_arrival_ns
+
+    def fetch(self):
+        """The request's outputs as numpy arrays (copied from the server's
+        device memory): record_offsets[R+1], field_offsets[F+1],
+        column_ids[F], and per column values/valid/str_end of R entries."""
+        import numpy as np
+        o = self._out.out
+        R = min(self.result["num_records"], o.cap_records)
+        F = min(self.result["num_fields"], o.cap_fields)
+        got = {"record_offsets": device_to_numpy(o.d_record_offsets, R + 1, np.int64),
+               "field_offsets": device_to_numpy(o.d_field_offsets, F + 1, np.int64),
+               "column_ids": device_to_numpy(o.d_column_ids, F, np.int32),
+               "values": [], "valid": [], "str_end": []}
+        nc = len(self.types)
+        vals = ctypes.cast(o.d_values, ctypes.POINTER(ctypes.c_void_p))
+        vmask = ctypes.cast(o.d_valid, ctypes.POINTER(ctypes.c_void_p))
+        ends = ctypes.cast(o.d_str_end, ctypes.POINTER(ctypes.c_void_p))
+        for c in range(nc):
+            ty = self.types[c]
+            if ty == SKIP:
+                got["values"].append(None); got["valid"].append(None); got["str_end"].append(None)
+                continue
+            got["values"].append(device_to_numpy(vals[c], R, np.float64 if ty == FLOAT64 else np.int64))
+            got["valid"].append(device_to_numpy(vmask[c], R, np.uint8))
+            got["str_end"].append(device_to_numpy(ends[c], R, np.int64) if ty == STRING else None)
+        return got
+
+
+class Server:
+    """Request loop over pinned host inputs (pp_server_*). ``dfas`` are the
+    dialects requests refer to by index."""
+
+    def __init__(self, dfas, hbm_budget_bytes: int, max_slots: int = 64, copy_streams: int = 2,
+                 compute_streams: int = 2, max_batch: int = 0, opts: Optional[PpOptions] = None):
+        self._dfas = (PpDfa * len(dfas))(*[dfa_struct(d) for d in dfas])
+        cfg = PpServerConfig(hbm_budget_bytes, max_slots, copy_streams, compute_streams, max_batch,
+                             opts if opts else PpOptions(0, 0))
+        h = ctypes.c_void_p()
+        _check(lib().pp_server_create(ctypes.byref(cfg), self._dfas, len(dfas), ctypes.byref(h)),
+               "pp_server_create")
+        self.handle = h
+        self._live = {}  # id -> (pinned tensor, types array, types list) kept alive until completion
+        self._buf = (PpServerCompletion * 256)()
+
+    def submit(self, h_in, dialect: int, types: Sequence[int], cap_records: int, cap_fields: int) -> int:
+        """``h_in``: a pinned uint8 CPU tensor, unchanged until completion."""
+        nc = len(types)
+        t = (ctypes.c_int32 * max(nc, 1))(*types)
+        n = int(h_in.numel())
+        rq = PpServerRequest(h_in.data_ptr() if n else None, n, dialect, nc, ctypes.cast(t, ctypes.c_void_p),
+                             cap_records, cap_fields)
+        rid = ctypes.c_uint64()
+        _check(lib().pp_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(rid)), "pp_server_submit")
+        self._live[rid.value] = (h_in, t, list(types))
+        return rid.value
+
+    def poll(self, max_items: int = 256) -> List[Completion]:
+        arr = self._buf
+        got = ctypes.c_int32()
+        _check(lib().pp_server_poll(self.handle, arr, min(max_items, len(arr)), ctypes.byref(got)),
+               "pp_server_poll")
+        out = []
+        for i in range(got.value):
+            c = arr[i]
+            keep = self._live.pop(c.id, (None, None, []))
+            cc = PpServerCompletion.from_buffer_copy(c)
+            out.append(Completion(c.id, c.n, {f: getattr(c.result, f) for f in RESULT_FIELDS},
+                                  c.t_arrival_ns, c.t_admit_ns, c.t_h2d_done_ns, c.t_parse_done_ns,
+                                  cc, keep[2]))
+        return out
+
+    def wait(self, timeout_us: int = 1000) -> None:
+        _check(lib().pp_server_wait(self.handle, timeout_us), "pp_server_wait")
+
+    def release(self, rid: int) -> None:
+        _check(lib().pp_server_release(self.handle, rid), "pp_server_release")
+
+    def stats(self) -> dict:
+        st = PpServerStats()
+        _check(lib().pp_server_get_stats(self.handle, ctypes.byref(st)), "pp_server_get_stats")
+        return {f: getattr(st, f) for f, _ in PpServerStats._fields_}
+
+    def close(self):
+        if self.handle:
+            lib().pp_server_destroy(self.handle)
+            self.handle = None
+            self._live.clear()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- launch-shape autotuner ----------------------------------------------------
+
+def shapes() -> List[PpOptions]:
+    out = []
+    for i in range(5):
+        o = PpOptions()
+        _check(lib().pp_shape(i, ctypes.byref(o)), "pp_shape")
+        out.append(o)
+    return out
+
+
+def _tune_cache_path(path=None):
+    return path or os.environ.get("PARPARAW_TUNE_CACHE",
+                                  os.path.join(os.path.expanduser("~"), ".cache", "parparaw", "tune.json"))
+
+
+def _tune_lookup(key, path):
+    import json
+    try:
+        with open(path) as f:
+            hit = json.load(f).get(key)
+    except (OSError, ValueError):
+        return None
+    if hit:
+        return PpOptions(hit["bytes_per_thread"], hit["block_threads"]), hit
+    return None
+
+
+def _tune_store(key, best, ms, path):
+    import json
+    d = {}
+    try:
+        with open(path) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        d = {}
+    d[key] = {"bytes_per_thread": best.bytes_per_thread, "block_threads": best.block_threads,
+              "ms": [round(float(x), 5) for x in ms]}
+    os.makedirs(os.path.dirname(path) or ".", exist_ok=True)
+    tmp = path + ".tmp"
+    with open(tmp, "w") as f:
+        json.dump(d, f, indent=1, sort_keys=True)
+    os.replace(tmp, path)
+    return d[key]
+
+
+def _device_tag():
+    import torch
+    p = torch.cuda.get_device_properties(torch.cuda.current_device())
+    return f"{getattr(p, 'gcnArchName', p.name)}/{p.multi_processor_count}cu"
+
+
+def _bucket(x: int) -> int:
+    return max(int(x), 1).bit_length()
+
+
+def batch_signature(dfas, items) -> str:
+    """Cache key of a batch: device, buffer count and total bytes (powers of
+    two), largest state count among the dialects used."""
+    total = sum(int(it[0].numel()) for it in items)
+    states = max((dfas[it[1]].num_states for it in items), default=0)
+    return f"{_device_tag()}|batch|n{_bucket(len(items))}|b{_bucket(total)}|s{states}"
+
+
+def autotune_batch(dfas, items, reps: int = 3, cache: Optional[str] = None, stream=None, retune: bool = False):
+    """Fastest launch shape for this batch (pp_batch_autotune), cached in a
+    JSON file by batch_signature(). Returns (PpOptions, record)."""
+    import torch
+    path = _tune_cache_path(cache)
+    key = batch_signature(dfas, items)
+    if not retune:
+        hit = _tune_lookup(key, path)
+        if hit:
+            return hit
+    L = lib()
+    d = (PpDfa * len(dfas))(*[dfa_struct(x) for x in dfas])
+    arr, keep = _batch_items(items)
+    size = int(L.pp_batch_autotune_workspace_size(d, len(dfas), arr, len(items)))
+    dev = items[0][0].device if items else torch.device("cuda")
+    ws = torch.empty(max(size, 1), dtype=torch.uint8, device=dev)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    best = PpOptions()
+    ms = (ctypes.c_float * 5)()
+    _check(L.pp_batch_autotune(d, len(dfas), arr, len(items), ws.data_ptr(), ws.numel(), reps,
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best), ms), "pp_batch_autotune")
+    return best, _tune_store(key, best, list(ms), path)
+
+
+def autotune_parse(d_in, dfa, types: Sequence[int], out: Outputs, reps: int = 3, cache: Optional[str] = None,
+                   stream=None, retune: bool = False):
+    """Fastest launch shape for pp_parse of this input (pp_parse_autotune),
+    cached by device, size (power of two), state count and column count."""
+    import torch
+    path = _tune_cache_path(cache)
+    n = int(d_in.numel())
+    key = f"{_device_tag()}|parse|b{_bucket(n)}|s{dfa.num_states}|c{len(types)}"
+    if not retune:
+        hit = _tune_lookup(key, path)
+        if hit:
+            return hit
+    L = lib()
+    ws = torch.empty(max(int(L.pp_autotune_workspace_size(n)), 1), dtype=torch.uint8, device=d_in.device)
+    call = Call(d_in, n, dfa, types, out, ws)
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    best = PpOptions()
+    ms = (ctypes.c_float * 5)()
+    _check(L.pp_parse_autotune(d_in.data_ptr() if n else None, n, ctypes.byref(call.dfa), ctypes.byref(call.schema),
+                               ctypes.byref(call.outs), ws.data_ptr(), ws.numel(), reps,
+                               ctypes.c_void_p(stream.cuda_stream), ctypes.byref(best), ms), "pp_parse_autotune")
+    return best, _tune_store(key, best, list(ms), path)

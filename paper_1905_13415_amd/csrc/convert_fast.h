@@ -56,64 +56,88 @@ __device__ __forceinline__ Win load_win_padded(const uint32_t* lds_words, int of
 }
 
 // Byte-serial parses over a left-aligned window (the field starts at byte 0),
-// fully unrolled; bytes past a lane's field are masked off, and the body is
-// skipped once no lane of the wavefront is still inside its field.
+// fully unrolled and branch-free per byte (selects, no divergent ifs); the
+// loop ends once no lane of the wavefront is still inside its field.
+__device__ __forceinline__ bool wave_any(bool p) { return __builtin_amdgcn_ballot_w64(p) != 0; }
+
 __device__ __forceinline__ int ser_int64(const Win& x, int len, int64_t* out)
 {
     const uint32_t c0 = x.at(0);
     const bool neg = c0 == '-';
-    const int s = (c0 == '+' || c0 == '-') ? 1 : 0;
-    if (len - s > 18) return -1;  // overflow checks in the general path
-    if (len <= s) return 0;
+    const bool sg = (c0 == '+') | (c0 == '-');
+    if (len - (int)sg > 18) return -1;  // overflow checks in the general path
+    if (len <= (int)sg) return 0;
+    uint32_t m32 = 0;  // the first nine bytes fit 32 bits
     uint64_t mag = 0;
     bool bad = false;
 #pragma unroll
-    for (int i = 0; i < 19; ++i) {
-        if (i < len && i >= s) {
+    for (int q = 0; q < 5; ++q) {  // a dword of the window per step (19 bytes at most)
+        if (!wave_any(4 * q < len)) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * q + j;
+            if (i >= 19) break;
             const uint32_t d = x.at(i) - '0';
-            bad |= d > 9u;
-            mag = mag * 10u + d;
+            const bool in = i == 0 ? !sg : (i < len);
+            bad |= in & (d > 9u);
+            if (i < 9) {
+                m32 = in ? m32 * 10u + d : m32;
+                if (i == 8) mag = m32;
+            } else {
+                const uint64_t nx = mag * 10u + d;
+                mag = in ? nx : mag;
+            }
         }
     }
+    if (len <= 8) mag = m32;  // the loop may have ended before byte 8
     if (bad) return 0;
     *out = neg ? -(int64_t)mag : (int64_t)mag;
     return 1;
 }
 
 // [+-]?([0-9]+(\.[0-9]*)?|\.[0-9]+) with <= 19 digits and no exponent, in
-// Clinger's exact range; anything else goes to the general path.
+// Clinger's exact range (digit string below 2^53, at most 22 fraction
+// digits); anything else goes to the general path. The digit string is
+// accumulated in double precision: every partial value is an integer no
+// larger than the final one, so while the final value is below 2^53 each
+// step v*10+d is exact; a larger final value is caught by the range check
+// (rounding is monotonic, so it cannot land below 2^53).
 __device__ __forceinline__ int ser_float64(const Win& x, int len, double* out)
 {
     const uint32_t c0 = x.at(0);
     const bool neg = c0 == '-';
-    const int s = (c0 == '+' || c0 == '-') ? 1 : 0;
-    uint64_t w = 0;
-    int nd = 0, frac = 0;
-    bool dot = false, other = false;
+    const bool sg = (c0 == '+') | (c0 == '-');
+    double v = 0.0;
+    uint32_t dots = 0;  // bit i: byte i is a decimal point
+    bool other = false;
 #pragma unroll
-    for (int i = 0; i < kWin; ++i) {
-        if (i < len && i >= s) {
+    for (int q = 0; q < kWin / 4; ++q) {  // a dword of the window per step
+        if (!wave_any(4 * q < len)) break;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int i = 4 * q + j;
             const uint32_t c = x.at(i);
             const uint32_t d = c - '0';
-            if (d <= 9u) {
-                w = w * 10u + d;
-                ++nd;
-                frac += dot;
-            } else if (c == '.' && !dot) {
-                dot = true;
-            } else {
-                other = true;
-            }
+            const bool in = i == 0 ? (!sg & (len > 0)) : (i < len);
+            const bool isd = in & (d <= 9u);
+            const bool isdot = in & (c == '.');
+            other |= in & !isd & !isdot;
+            // a digit: v*10 + d; anything else: v*1 + 0 (no select of v needed)
+            const uint32_t dz = isd ? d : 0u;
+            v = __builtin_fma(v, isd ? 10.0 : 1.0, (double)dz);
+            dots = isdot ? dots | (1u << i) : dots;
         }
     }
-    if (other || nd > 19) return -1;
-    if (nd == 0) return 0;
-    if (w == 0) {
+    const int ndot = __popc(dots);
+    const int nd = len - (int)sg - ndot;  // digits, when nothing else is in the field
+    if (other || ndot > 1 || nd > 19) return -1;
+    if (nd <= 0) return 0;
+    if (v == 0.0) {
         *out = neg ? -0.0 : 0.0;
         return 1;
     }
-    if (w > (1ull << 53) || frac > 22) return -1;
-    double v = (double)w;
+    const int frac = ndot ? len - 1 - (31 - __clz((int)dots)) : 0;
+    if (!(v < 9007199254740992.0) || frac > 22) return -1;
     if (frac) v = v / exact_pow10(frac);
     *out = neg ? -v : v;
     return 1;
@@ -277,13 +301,36 @@ __device__ __forceinline__ uint32_t win_num(const Win& x, int p, int n, bool& ok
     return r;
 }
 
+// The calendar for four-digit years (0000-9999) in 32-bit arithmetic: the
+// same definitions as convert.h (Gregorian leap rule; Hinnant's era/day-of-
+// era count from March), with the year shifted by one 400-year era so that
+// every quantity stays non-negative.
+__device__ __forceinline__ uint32_t days_in_month4(uint32_t y, uint32_t m)
+{
+    // y % 400 == 0 exactly when y % 100 == 0 and y % 16 == 0
+    const bool leap = ((y & 3u) == 0) & ((y % 100u != 0) | ((y & 15u) == 0));
+    const uint32_t d = 30u + ((m + m / 8u) & 1u);
+    return m == 2 ? (leap ? 29u : 28u) : d;
+}
+
+__device__ __forceinline__ int64_t days_from_civil4(uint32_t y, uint32_t m, uint32_t d)
+{
+    const uint32_t ys = y + 400u - (m <= 2u);  // [399, 10399]
+    const uint32_t era = ys / 400u;
+    const uint32_t yoe = ys - era * 400u;
+    const uint32_t mp = m > 2u ? m - 3u : m + 9u;  // March = 0
+    const uint32_t doy = (153u * mp + 2u) / 5u + d - 1u;
+    const uint32_t doe = yoe * 365u + yoe / 4u - yoe / 100u + doy;
+    return (int64_t)era * 146097 + (int64_t)doe - 719468 - 146097;
+}
+
 __device__ __forceinline__ int win_date(const Win& x, int len, int64_t* out)
 {
     bool ok = (len == 10) & (x.at(4) == '-') & (x.at(7) == '-');
     const uint32_t y = win_num(x, 0, 4, ok), m = win_num(x, 5, 2, ok), d = win_num(x, 8, 2, ok);
     ok &= (m >= 1) & (m <= 12) & (d >= 1);
-    ok &= d <= (uint32_t)days_in_month(y, ok ? m : 1);
-    *out = ok ? days_from_civil(y, m, d) : 0;
+    ok &= d <= days_in_month4(y, ok ? m : 1);
+    *out = ok ? days_from_civil4(y, m, d) : 0;
     return ok;
 }
 
@@ -295,8 +342,8 @@ __device__ __forceinline__ int win_timestamp(const Win& x, int len, int64_t* out
     const uint32_t y = win_num(x, 0, 4, ok), m = win_num(x, 5, 2, ok), d = win_num(x, 8, 2, ok);
     const uint32_t h = win_num(x, 11, 2, ok), mi = win_num(x, 14, 2, ok), s = win_num(x, 17, 2, ok);
     ok &= (m >= 1) & (m <= 12) & (d >= 1) & (h <= 23) & (mi <= 59) & (s <= 59);
-    ok &= d <= (uint32_t)days_in_month(y, ok ? m : 1);
-    *out = ok ? days_from_civil(y, m, d) * 86400 + (int64_t)(h * 3600u + mi * 60u + s) : 0;
+    ok &= d <= days_in_month4(y, ok ? m : 1);
+    *out = ok ? days_from_civil4(y, m, d) * 86400 + (int64_t)(h * 3600u + mi * 60u + s) : 0;
     return ok;
 }
 

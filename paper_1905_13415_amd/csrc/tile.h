@@ -21,11 +21,12 @@
 //      same way;
 //   6. delimiter positions, column ids and record ends staged in LDS, then
 //      written coalesced as field offsets, column ids and record offsets;
-//   7. typed conversion (Sec. 3.3): the tile's (column, record) pairs are
-//      visited column-major, so a wavefront converts one column's type and
-//      its stores into that typed column are contiguous. This takes the place
-//      of the paper's radix-sort partition by column tag: the pair addresses
-//      the output slot directly.
+//   7. typed conversion (Sec. 3.3): a thread walks one record's fields of a
+//      contiguous group of columns; lanes of a wavefront hold consecutive
+//      records, so at each step they convert the same column (one type) and
+//      their stores into that typed column are contiguous. This takes the
+//      place of the paper's radix-sort partition by column tag: the (record,
+//      column) pair addresses the output slot directly.
 // Tiles with more fields or records than the LDS staging holds take a
 // per-thread path for steps 6-7 that gives the same outputs.
 // The input is read from HBM once; per-symbol metadata never leaves the chip.
@@ -52,6 +53,22 @@ struct ColDesc {
     int32_t type;
     int32_t pad;
 };
+
+// Device pointers of the outputs and the input are plain (generic) pointers
+// in the descriptors; at the access they are cast to the global address
+// space so that loads and stores compile to global (not flat) instructions,
+// which do not hold up waits on LDS results.
+#define PP_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ PP_GLOBAL T* gptr(T* ptr)
+{
+    return (PP_GLOBAL T*)ptr;
+}
+template <class T>
+__device__ __forceinline__ const PP_GLOBAL T* gptr(const T* ptr)
+{
+    return (const PP_GLOBAL T*)ptr;
+}
 
 // Output pointers of one column, as seen from a tile's first record.
 struct ColBase {
@@ -102,12 +119,12 @@ constexpr u64 kLastPos = (1ull << 56) - 1;
 
 __device__ inline void publish(u64* w, u64 v)
 {
-    __hip_atomic_store(w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(gptr(w), v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline u64 peek(u64* w)
 {
-    return __hip_atomic_load(w, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    return __hip_atomic_load(gptr(w), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 __device__ inline u64 ballot(bool x) { return __ballot(x); }
@@ -282,7 +299,7 @@ struct ByteSrc {
     __device__ uint32_t operator()(int64_t pos) const
     {
         int64_t r = pos - tile_start;
-        return r >= 0 ? lds[r] : g[pos];
+        return r >= 0 ? lds[r] : gptr(g)[pos];
     }
 };
 
@@ -290,6 +307,27 @@ __device__ inline int64_t wave_sum(int64_t v)
 {
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
     return v;
+}
+
+// The general conversions (any length, any position, exponents, more than
+// 19 digits). Returns 1 converted, 0 not a value of the type. (Kept inline:
+// out of line, the calls cost the whole kernel about 7% on the numeric
+// workload.)
+__device__ inline int convert_general(int ty, const ByteSrc& src, int64_t b, int64_t e, u64* bits)
+{
+    if (ty == PP_FLOAT64) {
+        double dv = 0.0;
+        const int r = conv_float64(src, b, e, &dv);
+        *bits = __builtin_bit_cast(u64, dv);
+        return r;
+    }
+    int64_t iv = 0;
+    int r;
+    if (ty == PP_INT64) r = conv_int64(src, b, e, &iv);
+    else if (ty == PP_TIMESTAMP_S) r = conv_timestamp(src, b, e, &iv);
+    else r = conv_date(src, b, e, &iv);
+    *bits = (u64)iv;
+    return r;
 }
 
 // Strip the enclosing control symbols of field [b, e) and convert it into
@@ -305,16 +343,16 @@ __device__ inline int store_field(const TileArgs& p, const ColDesc* cols, const 
     const ColDesc cd = cols[c];
     if (ty == PP_STRING) {
         if (store) {
-            ((int64_t*)cd.values)[rec] = begin;
-            cd.str_end[rec] = end;
-            cd.valid[rec] = 1;
+            gptr((int64_t*)cd.values)[rec] = begin;
+            gptr(cd.str_end)[rec] = end;
+            gptr(cd.valid)[rec] = 1;
         }
         return 0;
     }
     if (end == begin) {  // empty: the column default, not an error (Sec. 4.3)
         if (store) {
-            ((int64_t*)cd.values)[rec] = 0;
-            cd.valid[rec] = 0;
+            gptr((int64_t*)cd.values)[rec] = 0;
+            gptr(cd.valid)[rec] = 0;
         }
         return 0;
     }
@@ -360,8 +398,8 @@ __device__ inline int store_field(const TileArgs& p, const ColDesc* cols, const 
         bits = ok ? (u64)iv : 0ull;
     }
     if (store) {
-        ((u64*)cd.values)[rec] = bits;
-        cd.valid[rec] = ok;
+        gptr((u64*)cd.values)[rec] = bits;
+        gptr(cd.valid)[rec] = ok;
     }
     return !ok;
 }
@@ -370,9 +408,9 @@ __device__ inline void store_missing(const TileArgs& p, const ColDesc* cols, int
 {
     if (rec >= p.cap_records || ty == PP_SKIP) return;
     const ColDesc cd = cols[c];
-    ((u64*)cd.values)[rec] = 0;  // 0 and 0.0 share the bit pattern
-    cd.valid[rec] = 0;
-    if (ty == PP_STRING) cd.str_end[rec] = 0;
+    gptr((u64*)cd.values)[rec] = 0;  // 0 and 0.0 share the bit pattern
+    gptr(cd.valid)[rec] = 0;
+    if (ty == PP_STRING) gptr(cd.str_end)[rec] = 0;
 }
 
 // ---- the kernel ---------------------------------------------------------------
@@ -446,8 +484,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     // per-byte transition rows, precomputed by parse_init from the group table
     for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
-        s_tnext[k] = p.tables[k];
-        s_tcomb[k] = p.tables[512 + k];
+        s_tnext[k] = gptr(p.tables)[k];
+        s_tcomb[k] = gptr(p.tables)[512 + k];
     }
     for (int c = tid; c < p.ncols; c += NT) s_cols[c] = p.cols[c];
     __syncthreads();
@@ -464,9 +502,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
             u32x4* d4 = reinterpret_cast<u32x4*>(s_bytes);
 #pragma unroll
-            for (int k = tid; k < TILE / 16; k += NT) d4[k] = __builtin_nontemporal_load(s4 + k);
+            for (int k = tid; k < TILE / 16; k += NT) d4[k] = __builtin_nontemporal_load(gptr(s4) + k);
         } else {
-            for (int k = tid; k < TILE; k += NT) s_bytes[k] = k < tile_len ? src[k] : 0;
+            for (int k = tid; k < TILE; k += NT) s_bytes[k] = k < tile_len ? gptr(src)[k] : 0;
         }
     }
     __syncthreads();
@@ -607,7 +645,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 if (r8 == inv8) at = i;
             }
         }
-        p.result->first_invalid_offset = cstart + at;
+        gptr(p.result)->first_invalid_offset = cstart + at;
     }
 
     auto popc = [](M m) -> uint32_t {
@@ -678,6 +716,39 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     if (len > 0 && c0 + len == tile_len) s_ctl_last = (uint32_t)((cmask >> (len - 1)) & 1u);
     __syncthreads();
 
+    const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
+    const bool staged = Ft <= FCAP && Rt <= RCAP;
+    if (staged) {
+        // ---- 6a. stage the tile's structure in LDS (tile-local; done before the
+        // count lookback so that predecessors have time to publish): delimiter
+        // positions, column ids and record ends. Fields of the record open at
+        // the tile start carry column ids relative to the carried column C0,
+        // which the lookback supplies.
+        uint32_t L = cex.nf, lr = cex.nr;
+        uint32_t col = cex.col & ~kCAbs;
+#pragma unroll
+        for (int h = 0; h < (B > 32 ? 2 : 1); ++h) {
+            uint32_t m = (uint32_t)(dmask >> (32 * h));
+            const uint32_t rm = (uint32_t)(rmask >> (32 * h));
+            const uint32_t base = (uint32_t)c0 + 32u * h;
+            while (m) {
+                const uint32_t i = (uint32_t)__builtin_ctz(m);
+                m &= m - 1;
+                const bool isr = (rm >> i) & 1u;
+                s_pos[L] = (uint16_t)(base + i);
+                s_colid[L] = (uint16_t)col;
+                if (isr) s_recend[lr++] = (uint16_t)L;
+                col = isr ? 0u : col + 1u;
+                ++L;
+            }
+        }
+        if (vend) {
+            s_pos[L] = (uint16_t)tile_len;
+            s_colid[L] = (uint16_t)col;
+            s_recend[lr] = (uint16_t)L;
+        }
+    }
+
     if (wave == 0) {
         // this tile's aggregate, in the device representation
         const uint32_t lastrel = tagg.last;  // position + 1, 0 = none
@@ -702,14 +773,14 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 bool incl_ok = false, agg_ok = false;
                 int first;
                 for (;;) {
-                    if (j >= 0 && !incl_ok) {
+                    if (j >= 0 && !incl_ok) {  // all words of the tile in one round trip
                         ir = peek(pw + W_IREC); iF = peek(pw + W_IFLD);
                         ic = peek(pw + W_ICOL); il = peek(pw + W_ILAST);
-                        incl_ok = (ir >> 62) && (iF >> 62) && (ic >> 62) && (il >> 62);
-                        if (!incl_ok && !agg_ok) {
+                        if (!agg_ok) {
                             g0 = peek(pw + W_AGG0); g1 = peek(pw + W_AGG1);
-                            agg_ok = (g0 >> 62) && (g1 >> 62);
                         }
+                        incl_ok = (ir >> 62) && (iF >> 62) && (ic >> 62) && (il >> 62);
+                        agg_ok = agg_ok || ((g0 >> 62) && (g1 >> 62));
                     }
                     if (j < 0) incl_ok = true;  // before tile 0: the seed (never reached)
                     const u64 inc = ballot(incl_ok);
@@ -754,7 +825,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const int64_t F0 = (int64_t)s_pref[1];
     const int64_t C0 = (int64_t)(s_pref[2] & kColVal);  // always absolute: seeded with (abs, 0)
     const u64 lastw = s_pref[3];
-    const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
     const int ncols = p.ncols;
     const ByteSrc src{s_bytes, p.in, tile_start, TILE};
     const bool last_has = (lastw & kLastHas) != 0;
@@ -768,7 +838,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const int r = (int)(b - tile_start);
             return (s_ctl[r >> 5] >> (r & 31)) & 1u;
         }
-        const uint32_t by = p.in[b];
+        const uint32_t by = gptr(p.in)[b];
         const uint32_t s8 = last_sa * 8u;
         uint32_t x;
         if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (s8 >> 5)], s8 & 31u, 8);
@@ -784,33 +854,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     };
 
     int64_t nerr = 0, nragged = 0;
-    if (Ft <= FCAP && Rt <= RCAP && C0 + Ft < 65536) {
-        // ---- 6. emit structure through LDS --------------------------------------------------
-        {
-            uint32_t L = cex.nf, lr = cex.nr;
-            uint32_t col = (cex.col & kCAbs) ? (cex.col & ~kCAbs) : (uint32_t)C0 + cex.col;
-#pragma unroll
-            for (int h = 0; h < (B > 32 ? 2 : 1); ++h) {
-                uint32_t m = (uint32_t)(dmask >> (32 * h));
-                const uint32_t rm = (uint32_t)(rmask >> (32 * h));
-                const uint32_t base = (uint32_t)c0 + 32u * h;
-                while (m) {
-                    const uint32_t i = (uint32_t)__builtin_ctz(m);
-                    m &= m - 1;
-                    const bool isr = (rm >> i) & 1u;
-                    s_pos[L] = (uint16_t)(base + i);
-                    s_colid[L] = (uint16_t)col;
-                    if (isr) s_recend[lr++] = (uint16_t)L;
-                    col = isr ? 0u : col + 1u;
-                    ++L;
-                }
-            }
-            if (vend) {
-                s_pos[L] = (uint16_t)tile_len;
-                s_colid[L] = (uint16_t)col;
-                s_recend[lr] = (uint16_t)L;
-            }
-        }
+    if (staged) {
         if (tid < ncols) {  // column outputs as seen from this tile's first record
             const ColDesc d = s_cols[tid];
             s_cb[tid] = {(char*)d.values + R0 * 8, d.valid + R0, d.str_end + R0};
@@ -821,108 +865,116 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const int kf = roomf < Ft ? (int)(roomf < 0 ? 0 : roomf) : Ft;
             int64_t* const fo = p.field_offsets + F0 + 1;
             int32_t* const ci = p.column_ids + F0;
+            const int open_end = Rt ? (int)s_recend[0] + 1 : Ft;  // fields of the record open at the tile start
             for (int k = tid; k < kf; k += NT) {
-                fo[k] = tile_start + 1 + s_pos[k];
-                ci[k] = s_colid[k];
+                gptr(fo)[k] = tile_start + 1 + s_pos[k];
+                gptr(ci)[k] = (int32_t)s_colid[k] + (k < open_end ? (int32_t)C0 : 0);
             }
             const int64_t roomr = p.cap_records - R0;
             const int kr = roomr < Rt ? (int)(roomr < 0 ? 0 : roomr) : Rt;
             int64_t* const ro = p.record_offsets + R0 + 1;
-            for (int k = tid; k < kr; k += NT) ro[k] = F0 + 1 + s_recend[k];
+            for (int k = tid; k < kr; k += NT) gptr(ro)[k] = F0 + 1 + s_recend[k];
         }
 
-        // ---- 7. typed columns, column-major over (column, local record) ------------------
+        // ---- 7. typed columns ---------------------------------------------------------------
+        // A thread takes one record of the tile (the records it closes, plus
+        // the open one) and a contiguous group of its columns; lanes of a
+        // wavefront hold consecutive records of the same group, so at every
+        // step they convert the same column (one type, no divergence) and
+        // their stores into that typed column are contiguous. Walking a
+        // group's fields in order reads one delimiter position per field.
         const uint32_t nrec = (uint32_t)Rt + 1u;  // records closed here plus the open one
-        const uint32_t items = nrec * (uint32_t)ncols;
         const int64_t roomr = p.cap_records - R0;
         const uint32_t lr_cap = roomr <= 0 ? 0u : (roomr > (int64_t)nrec ? nrec : (uint32_t)roomr);
         const bool anyctl = s_anyctl != 0;
         const uint32_t* const words = reinterpret_cast<const uint32_t*>(s_bytes);
-        const uint32_t dq = (uint32_t)NT / nrec, dr = (uint32_t)NT % nrec;
-        uint32_t c = (uint32_t)tid / nrec, lr = (uint32_t)tid % nrec;
-        for (uint32_t q = tid; q < items; q += NT) {
+        uint32_t groups = (uint32_t)NT / nrec;
+        groups = groups < 1u ? 1u : (groups > (uint32_t)ncols ? (uint32_t)ncols : groups);
+        const uint32_t per = ncols ? ((uint32_t)ncols + groups - 1u) / groups : 0u;  // columns per group
+        groups = per ? ((uint32_t)ncols + per - 1u) / per : 0u;
+        const uint32_t work = nrec * groups;
+        for (uint32_t w = tid; w < work; w += NT) {
+            const uint32_t g = w / nrec, lr = w - g * nrec;
             const uint32_t first = lr ? s_recend[lr - 1] + 1u : 0u;
             const uint32_t end1 = lr < (uint32_t)Rt ? s_recend[lr] + 1u : (uint32_t)Ft;  // one past the last field
-            const uint32_t cf = lr ? 0u : (uint32_t)C0;
-            if (c == 0 && lr < (uint32_t)Rt && cf + end1 - first != (uint32_t)ncols) ++nragged;
-            const uint32_t ty = s_cols[c].type;
-            if (c >= cf && ty != PP_SKIP) {
+            // the open record from the previous tile continues at column C0 (any
+            // C0 >= 65535 is beyond every schema column)
+            const uint32_t cf = lr ? 0u : (C0 < 65535 ? (uint32_t)C0 : 65535u);
+            if (g == 0 && lr < (uint32_t)Rt && cf + end1 - first != (uint32_t)ncols) ++nragged;
+            const uint32_t cb = g * per;
+            const uint32_t ce = cb + per < (uint32_t)ncols ? cb + per : (uint32_t)ncols;
+            const bool st = lr < lr_cap;
+            int pend = -1;  // position of the delimiter before the next field, once known
+            for (uint32_t c = cb; c < ce; ++c) {
+                if (c < cf) continue;
                 const uint32_t L = first + c - cf;
+                const uint32_t ty = s_cols[c].type;
                 if (L >= end1) {
-                    if (lr < (uint32_t)Rt && lr < lr_cap) {  // missing column of a short record
+                    if (lr < (uint32_t)Rt && st && ty != PP_SKIP) {  // missing column of a short record
                         const ColBase cd = s_cb[c];
-                        ((u64*)cd.values)[lr] = 0;
-                        cd.valid[lr] = 0;
-                        if (ty == PP_STRING) cd.str_end[lr] = 0;
+                        gptr((u64*)cd.values)[lr] = 0;
+                        gptr(cd.valid)[lr] = 0;
+                        if (ty == PP_STRING) gptr(cd.str_end)[lr] = 0;
                     }
-                } else if (L == 0) {  // may begin in an earlier tile: general path
+                    continue;
+                }
+                if (L == 0) {  // may begin in an earlier tile: general path
                     const int64_t e = tile_start + s_pos[0];
-                    const int64_t bb = last_has ? last_pos + 1 : 0;
-                    const bool cfst = e > bb && ctl_at_begin(bb);
-                    const bool clst = e > bb && ctl_at_end(e);
-                    nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, bb, e, cfst, clst);
-                } else {
-                    int bb = s_pos[L - 1] + 1, ee = s_pos[L];
-                    if (anyctl && ee > bb) {  // strip enclosing control symbols
-                        if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
-                        if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
+                    pend = s_pos[0];
+                    if (ty != PP_SKIP) {
+                        const int64_t bb = last_has ? last_pos + 1 : 0;
+                        const bool cfst = e > bb && ctl_at_begin(bb);
+                        const bool clst = e > bb && ctl_at_end(e);
+                        nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, bb, e, cfst, clst);
                     }
-                    const ColBase cd = s_cb[c];
-                    const bool st = lr < lr_cap;
-                    if (ty == PP_STRING) {
-                        if (st) {
-                            ((int64_t*)cd.values)[lr] = tile_start + bb;
-                            cd.str_end[lr] = tile_start + ee;
-                            cd.valid[lr] = 1;
+                    continue;
+                }
+                int bb = (pend >= 0 ? pend : (int)s_pos[L - 1]) + 1;
+                int ee = s_pos[L];
+                pend = ee;
+                if (ty == PP_SKIP) continue;
+                if (anyctl && ee > bb) {  // strip enclosing control symbols
+                    if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
+                    if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
+                }
+                const ColBase cd = s_cb[c];
+                if (ty == PP_STRING) {
+                    if (st) {
+                        gptr((int64_t*)cd.values)[lr] = tile_start + bb;
+                        gptr(cd.str_end)[lr] = tile_start + ee;
+                        gptr(cd.valid)[lr] = 1;
+                    }
+                } else if (ee == bb) {  // empty: the column default, not an error
+                    if (st) {
+                        gptr((u64*)cd.values)[lr] = 0;
+                        gptr(cd.valid)[lr] = 0;
+                    }
+                } else {
+                    const int len = ee - bb;
+                    int r = -1;
+                    u64 bits = 0;
+                    if (len <= kWin) {
+                        const Win x = load_win_padded(words, bb);
+                        if (ty == PP_FLOAT64) {
+                            double dv = 0.0;
+                            r = ser_float64(x, len, &dv);
+                            bits = __builtin_bit_cast(u64, dv);
+                        } else {
+                            int64_t iv = 0;
+                            if (ty == PP_INT64) r = ser_int64(x, len, &iv);
+                            else if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
+                            else r = win_date(x, len, &iv);
+                            bits = (u64)iv;
                         }
-                    } else if (ee == bb) {  // empty: the column default, not an error
-                        if (st) {
-                            ((u64*)cd.values)[lr] = 0;
-                            cd.valid[lr] = 0;
-                        }
-                    } else {
-                        const int len = ee - bb;
-                        int r = -1;
-                        u64 bits = 0;
-                        if (len <= kWin) {
-                            const Win x = load_win_padded(words, bb);
-                            if (ty == PP_FLOAT64) {
-                                double dv = 0.0;
-                                r = ser_float64(x, len, &dv);
-                                bits = __builtin_bit_cast(u64, dv);
-                            } else {
-                                int64_t iv = 0;
-                                if (ty == PP_INT64) r = ser_int64(x, len, &iv);
-                                else if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
-                                else r = win_date(x, len, &iv);
-                                bits = (u64)iv;
-                            }
-                        }
-                        if (r < 0) {
-                            const int64_t gb = tile_start + bb, ge = tile_start + ee;
-                            if (ty == PP_FLOAT64) {
-                                double dv = 0.0;
-                                r = conv_float64(src, gb, ge, &dv);
-                                bits = __builtin_bit_cast(u64, dv);
-                            } else {
-                                int64_t iv = 0;
-                                if (ty == PP_INT64) r = conv_int64(src, gb, ge, &iv);
-                                else if (ty == PP_TIMESTAMP_S) r = conv_timestamp(src, gb, ge, &iv);
-                                else r = conv_date(src, gb, ge, &iv);
-                                bits = (u64)iv;
-                            }
-                        }
-                        nerr += r == 0;
-                        if (st) {
-                            ((u64*)cd.values)[lr] = r ? bits : 0ull;
-                            cd.valid[lr] = (uint8_t)r;
-                        }
+                    }
+                    if (r < 0) r = convert_general((int)ty, src, tile_start + bb, tile_start + ee, &bits);
+                    nerr += r == 0;
+                    if (st) {
+                        gptr((u64*)cd.values)[lr] = r ? bits : 0ull;
+                        gptr(cd.valid)[lr] = (uint8_t)r;
                     }
                 }
             }
-            lr += dr;
-            c += dq;
-            if (lr >= nrec) { lr -= nrec; ++c; }
         }
         if (ncols == 0 && tid == 0) nragged = Rt;
     } else {
@@ -946,8 +998,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 isrec = true;
             }
             const int64_t f = F0 + L;
-            if (f + 1 <= p.cap_fields) p.field_offsets[f + 1] = pos + 1;
-            if (f < p.cap_fields) p.column_ids[f] = (int32_t)col;
+            if (f + 1 <= p.cap_fields) gptr(p.field_offsets)[f + 1] = pos + 1;
+            if (f < p.cap_fields) gptr(p.column_ids)[f] = (int32_t)col;
             const int64_t rec = R0 + lr;
             if (col < ncols) {
                 const int ty = s_cols[col].type;
@@ -961,7 +1013,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             if (isrec) {
                 if (col + 1 != ncols) ++nragged;
                 for (int64_t c = col + 1; c < ncols; ++c) store_missing(p, s_cols, (int)c, s_cols[c].type, rec);
-                if (rec + 1 <= p.cap_records) p.record_offsets[rec + 1] = f + 1;
+                if (rec + 1 <= p.cap_records) gptr(p.record_offsets)[rec + 1] = f + 1;
                 ++lr;
                 col = 0;
             } else {
@@ -980,7 +1032,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
     if (tid == 0) {
-        if (s_err) atomicAdd((u64*)&p.result->num_conversion_errors, s_err);
+        if (s_err) atomicAdd((u64*)&p.result->num_conversion_errors, s_err);  // rare: generic is fine
         if (s_ragged) atomicAdd((u64*)&p.result->num_ragged_records, s_ragged);
         if (tile == (uint32_t)p.num_tiles - 1) {
             const int64_t R = R0 + Rt, F = F0 + Ft;
@@ -990,10 +1042,11 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             else if (p.invalid_state >= 0 && fin == (uint32_t)p.invalid_state) st = PP_RESULT_INVALID_INPUT;
             else if (!((p.accept_mask >> fin) & 1u)) st = PP_RESULT_NON_ACCEPTING_END;
             else st = PP_RESULT_OK;
-            p.result->num_records = R;
-            p.result->num_fields = F;
-            p.result->final_state = fin;
-            p.result->status = st;
+            PP_GLOBAL pp_result_t* res = gptr(p.result);
+            res->num_records = R;
+            res->num_fields = F;
+            res->final_state = fin;
+            res->status = st;
         }
     }
 }

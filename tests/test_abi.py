@@ -82,3 +82,33 @@ def test_argument_errors_are_synchronous():
     assert _call(good, opts=pp.options(48, 256)) == -1
     assert _call(good, opts=pp.options(32, 128)) == -1
     assert _call(good, opts=pp.options(64, 1024)) == -1
+
+
+def test_shapes_and_autotune_workspace():
+    got = [(o.block_threads, o.bytes_per_thread) for o in pp.shapes()]
+    assert got == [(512, 64), (256, 64), (512, 32), (256, 32), (256, 16)]
+    L = pp.lib()
+    assert L.pp_shape(5, ctypes.byref(pp.PpOptions())) == -1
+    for n in (0, 1, 32768, 1 << 20, (1 << 20) + 3):
+        assert L.pp_autotune_workspace_size(n) == max(pp.workspace_size(n, o) for o in pp.shapes())
+
+
+def test_server_argument_errors_without_device():
+    L = pp.lib()
+    h = ctypes.c_void_p()
+    dfa = pp.dfa_struct(D.csv4())
+    cfg = pp.PpServerConfig(1 << 30, 4, 2, 2, 0, pp.PpOptions(0, 0))
+    assert L.pp_server_create(None, ctypes.byref(dfa), 1, ctypes.byref(h)) == -1
+    assert L.pp_server_create(ctypes.byref(cfg), ctypes.byref(dfa), 0, ctypes.byref(h)) == -1
+    for bad in (pp.PpServerConfig(1 << 20, 4, 2, 2, 0, pp.PpOptions(0, 0)),   # budget below 64 MiB
+                pp.PpServerConfig(1 << 30, 0, 2, 2, 0, pp.PpOptions(0, 0)),   # no slots
+                pp.PpServerConfig(1 << 30, 4, 5, 2, 0, pp.PpOptions(0, 0)),   # too many copy streams
+                pp.PpServerConfig(1 << 30, 4, 2, 3, 0, pp.PpOptions(0, 0)),   # too many compute streams
+                pp.PpServerConfig(1 << 30, 4, 2, 2, 0, pp.PpOptions(48, 0))):  # no such shape
+        assert L.pp_server_create(ctypes.byref(bad), ctypes.byref(dfa), 1, ctypes.byref(h)) == -1
+    bad_dfa = pp.dfa_struct(D.csv4())
+    bad_dfa.start_state = 9
+    assert L.pp_server_create(ctypes.byref(cfg), ctypes.byref(bad_dfa), 1, ctypes.byref(h)) == -2
+    assert L.pp_server_submit(None, None, None) == -1
+    assert L.pp_server_release(None, 1) == -1
+    assert pp.lib().pp_status_str(-7) == b"larger than the device budget"

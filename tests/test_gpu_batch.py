@@ -102,3 +102,38 @@ def test_batch_equals_single_launches():
             if a is not None:
                 assert torch.equal(a.view(torch.int64), b.view(torch.int64))
     batch.close()
+
+
+def test_autotune_batch_and_cache(tmp_path):
+    cache = str(tmp_path / "tune.json")
+    dfas, items, refs, batch = _make_batch(32, 1 << 10, 400 << 10, seed=14)
+    batch.close()
+    best, rec = pp.autotune_batch(dfas, items, reps=2, cache=cache)
+    shapes = [(o.bytes_per_thread, o.block_threads) for o in pp.shapes()]
+    assert (best.bytes_per_thread, best.block_threads) in shapes
+    assert len(rec["ms"]) == 5 and all(m > 0 for m in rec["ms"])
+    assert rec["ms"][shapes.index((best.bytes_per_thread, best.block_threads))] == min(rec["ms"])
+    torch.cuda.synchronize()
+    _check_all(items, refs, "after autotune")  # every shape gives the same outputs
+    # second call: served from the cache file, same answer
+    again, rec2 = pp.autotune_batch(dfas, items, cache=cache)
+    assert (again.bytes_per_thread, again.block_threads) == (best.bytes_per_thread, best.block_threads)
+    assert rec2["ms"] == rec["ms"]
+    tuned = pp.Batch(dfas, items, opts=best)
+    tuned.launch()
+    torch.cuda.synchronize()
+    _check_all(items, refs, "tuned launch")
+    tuned.close()
+
+
+def test_autotune_parse(tmp_path):
+    g = datagen.c1()
+    dfa = D.csv4()
+    types = list(D.SCHEMA_C1.types)
+    ref = oracle.parse(g.data, dfa, types)
+    d_in = torch.from_numpy(g.data).cuda()
+    out = pp.alloc_outputs(types, ref.num_records, ref.num_fields)
+    best, rec = pp.autotune_parse(d_in, dfa, types, out, reps=2, cache=str(tmp_path / "t.json"))
+    assert all(m > 0 for m in rec["ms"])
+    torch.cuda.synchronize()
+    compare(ref, out, out.result_dict(), types, tag="after parse autotune")

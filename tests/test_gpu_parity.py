@@ -246,3 +246,31 @@ def test_repeated_runs_identical():
     assert torch.equal(out1.field_offsets, out2.field_offsets)
     for a, b in zip(out1.values, out2.values):
         assert torch.equal(a.view(torch.int64), b.view(torch.int64))
+
+
+def test_int_every_length_and_sign():
+    """Integers of 1 to 20 digits with and without signs (the register path
+    accumulates the first nine bytes in 32 bits, the rest in 64)."""
+    rnd = random.Random(5)
+    rows = []
+    for n in range(1, 21):
+        for _ in range(40):
+            digits = str(rnd.randint(1, 9)) + "".join(rnd.choice("0123456789") for _ in range(n - 1))
+            sign = rnd.choice(["", "-", "+"])
+            rows.append(sign + digits)
+            rows.append(sign + "0" * rnd.randint(0, 3) + digits[: max(1, n // 2)])
+    data = ("\n".join(f"{v},{i}" for i, v in enumerate(rows)) + "\n").encode()
+    assert_same(u8(data), D.csv4(), [D.INT64, D.INT64])
+
+
+def test_timestamps_all_years():
+    """Timestamps and dates drawn over years 0000-9999 (four-digit years)."""
+    rnd = random.Random(6)
+    rows = []
+    for _ in range(20000):
+        y, mo, d = rnd.randint(0, 9999), rnd.randint(1, 12), rnd.randint(1, 31)
+        h, mi, s = rnd.randint(0, 23), rnd.randint(0, 59), rnd.randint(0, 59)
+        sep = rnd.choice([" ", "T"])
+        rows.append(f"{y:04d}-{mo:02d}-{d:02d}{sep}{h:02d}:{mi:02d}:{s:02d},{y:04d}-{mo:02d}-{d:02d}")
+    data = ("\n".join(rows) + "\n").encode()
+    assert_same(u8(data), D.csv4(), [D.TIMESTAMP_S, D.DATE_DAYS])
