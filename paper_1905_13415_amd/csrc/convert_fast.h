@@ -55,6 +55,31 @@ __device__ __forceinline__ Win load_win_padded(const uint32_t* lds_words, int of
     return r;
 }
 
+// Bytes [off, off + kWin) of a padded LDS buffer, fetched in two steps: the
+// first 8 bytes always, the rest only when a lane of the wavefront has a
+// field longer than 8 bytes (bytes past 8 read as zero otherwise; the parses
+// below never look at them then).
+__device__ __forceinline__ Win load_win_lazy(const uint32_t* lds_words, int off, int len)
+{
+    const int d0 = off >> 2;
+    const uint32_t sh = (uint32_t)(off & 3);
+    Win r;
+    const uint32_t a0 = lds_words[d0], a1 = lds_words[d0 + 1], a2 = lds_words[d0 + 2];
+    r.w[0] = __builtin_amdgcn_alignbyte(a1, a0, sh);
+    r.w[1] = __builtin_amdgcn_alignbyte(a2, a1, sh);
+#pragma unroll
+    for (int k = 2; k < kWin / 4; ++k) r.w[k] = 0u;
+    if (__builtin_amdgcn_ballot_w64(len > 8) != 0) {
+        uint32_t raw[kWin / 4 + 1];
+        raw[2] = a2;
+#pragma unroll
+        for (int k = 3; k <= kWin / 4; ++k) raw[k] = lds_words[d0 + k];
+#pragma unroll
+        for (int k = 2; k < kWin / 4; ++k) r.w[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], sh);
+    }
+    return r;
+}
+
 // Byte-serial parses over a left-aligned window (the field starts at byte 0),
 // fully unrolled and branch-free per byte (selects, no divergent ifs); the
 // loop ends once no lane of the wavefront is still inside its field.

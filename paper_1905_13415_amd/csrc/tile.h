@@ -954,7 +954,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     int r = -1;
                     u64 bits = 0;
                     if (len <= kWin) {
-                        const Win x = load_win_padded(words, bb);
+                        const Win x = load_win_lazy(words, bb, len);
                         if (ty == PP_FLOAT64) {
                             double dv = 0.0;
                             r = ser_float64(x, len, &dv);
