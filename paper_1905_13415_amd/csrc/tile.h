@@ -718,6 +718,22 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 
     const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
     const bool staged = Ft <= FCAP && Rt <= RCAP;
+
+    // this tile's count aggregate in the device representation, published
+    // before any further work so that successors waiting on it see it early
+    const u64 a0 = ((u64)tagg.nr << 31) | tagg.nf;
+    u64 a1;
+    {
+        const uint32_t lastrel = tagg.last;  // position + 1, 0 = none
+        const u64 colw = (tagg.col & kCAbs) ? ((1ull << 30) | (tagg.col & ~kCAbs)) : tagg.col;
+        u64 lastw = s_ctl_last ? (1ull << 29) : 0ull;
+        if (lastrel) lastw |= (1ull << 30) | ((u64)s_last_sa << 25) | (u64)(lastrel - 1);
+        a1 = (colw << 31) | lastw;
+    }
+    if (tid == 0 && tile > 0) {
+        publish(tw + W_AGG0, kAgg | a0);
+        publish(tw + W_AGG1, kAgg | a1);
+    }
     if (staged) {
         // ---- 6a. stage the tile's structure in LDS (tile-local; done before the
         // count lookback so that predecessors have time to publish): delimiter
@@ -750,20 +766,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
 
     if (wave == 0) {
-        // this tile's aggregate, in the device representation
-        const uint32_t lastrel = tagg.last;  // position + 1, 0 = none
-        const u64 a0 = ((u64)tagg.nr << 31) | tagg.nf;
-        const u64 colw = (tagg.col & kCAbs) ? ((1ull << 30) | (tagg.col & ~kCAbs)) : tagg.col;
-        u64 lastw = s_ctl_last ? (1ull << 29) : 0ull;
-        if (lastrel) lastw |= (1ull << 30) | ((u64)s_last_sa << 25) | (u64)(lastrel - 1);
-        const u64 a1 = (colw << 31) | lastw;
         const Tot mineT = tot_from_agg(a0, a1, tile_start);
         Tot pre = {0ull, 0ull, kColAbs, 0ull};  // seed: record 0, field 0, column (abs, 0)
         if (tile > 0) {
-            if (lane == 0) {
-                publish(tw + W_AGG0, kAgg | a0);
-                publish(tw + W_AGG1, kAgg | a1);
-            }
             bool have = false;
             Tot acc;
             for (int64_t base = (int64_t)tile - 1;; base -= 64) {
