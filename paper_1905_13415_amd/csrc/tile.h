@@ -430,7 +430,9 @@ struct TileSmem {
     uint16_t recend[RCAP];  // local field index of each record delimiter
     uint32_t ctl[TILE / 32];  // control-symbol bitmap of the tile
     ColDesc cols[PP_MAX_COLUMNS];
-    ColBase cb[PP_MAX_COLUMNS];  // column outputs offset to this tile's first record
+    // column outputs offset to this tile's first record, as separate arrays of
+    // 8-byte entries (cheap 32-bit LDS indexing)
+    u64 cbv[PP_MAX_COLUMNS], cbm[PP_MAX_COLUMNS], cbe[PP_MAX_COLUMNS];
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
     uint32_t anyctl, s0, fin, last_sa, ctl_last;
@@ -458,7 +460,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     uint16_t* const s_recend = sm.recend;
     uint32_t* const s_ctl = sm.ctl;
     ColDesc* const s_cols = sm.cols;
-    ColBase* const s_cb = sm.cb;
+    u64* const s_cbv = sm.cbv;
+    u64* const s_cbm = sm.cbm;
+    u64* const s_cbe = sm.cbe;
     SV<NS8>* const s_wsv = reinterpret_cast<SV<NS8>*>(&sm.wsv[0][0]);
     Cnt* const s_wcnt = sm.wcnt;
     uint32_t& s_anyctl = sm.anyctl;
@@ -862,7 +866,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     if (staged) {
         if (tid < ncols) {  // column outputs as seen from this tile's first record
             const ColDesc d = s_cols[tid];
-            s_cb[tid] = {(char*)d.values + R0 * 8, d.valid + R0, d.str_end + R0};
+            s_cbv[tid] = (u64)((char*)d.values + R0 * 8);
+            s_cbm[tid] = (u64)(d.valid + R0);
+            s_cbe[tid] = (u64)(d.str_end + R0);
         }
         __syncthreads();
         {
@@ -916,7 +922,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 const uint32_t ty = s_cols[c].type;
                 if (L >= end1) {
                     if (lr < (uint32_t)Rt && st && ty != PP_SKIP) {  // missing column of a short record
-                        const ColBase cd = s_cb[c];
+                        const ColBase cd = {(void*)s_cbv[c], (uint8_t*)s_cbm[c], (int64_t*)s_cbe[c]};
                         gptr((u64*)cd.values)[lr] = 0;
                         gptr(cd.valid)[lr] = 0;
                         if (ty == PP_STRING) gptr(cd.str_end)[lr] = 0;
@@ -942,7 +948,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
                     if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
                 }
-                const ColBase cd = s_cb[c];
+                const ColBase cd = {(void*)s_cbv[c], (uint8_t*)s_cbm[c], (int64_t*)s_cbe[c]};
                 if (ty == PP_STRING) {
                     if (st) {
                         gptr((int64_t*)cd.values)[lr] = tile_start + bb;
