@@ -75,8 +75,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many launches (for rocprofv3), no JSON")
-    ap.add_argument("--workload", choices=["c2", "c4", "c5"], default="c2",
-                    help="c2: 1 GiB numeric CSV, plain launch (default); "
+    ap.add_argument("--workload", choices=["c1", "c2", "c4", "c5"], default="c2",
+                    help="c1: 10,000-record RFC-4180 CSV, latency of one plain launch; "
+                         "c2: 1 GiB numeric CSV, plain launch (default); "
                          "c4: 4,096 mixed-dialect buffers, batched launch against plain launches; "
                          "c5: request loop over pinned host inputs, p50/p99 latency")
     ap.add_argument("--c5-requests", type=int, default=2000)
@@ -91,6 +92,8 @@ def main():
               f"(the parse shards by byte range with one small all-gather; see DESIGN.md)",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "c1":
+        return bench_c1(args)
     if args.workload == "c4":
         return bench_c4(args)
     if args.workload == "c5":
@@ -219,6 +222,85 @@ def main():
                                 "kind": "oracle",
                                 "sample": f"the whole {n}-byte workload, one sequential oracle parse "
                                           f"({cpu_s:.1f} s, outputs preallocated)"}
+    print(json.dumps(line), flush=True)
+
+
+def bench_c1(args):
+    """Latency of one plain launch on the small quoted workload (10,000
+    records x 8 columns, ~1.34 MB, 20% of strings quoted with embedded
+    delimiters, newlines and doubled quotes): a handful of tiles, so the time
+    is one tile's pipeline plus launch overhead, not bandwidth."""
+    import torch
+
+    import datagen
+    import paper_1905_13415_amd as pp
+    from datagen import dialects as D
+
+    g = datagen.c1()
+    types = list(D.SCHEMA_C1.types)
+    dfa = D.csv4()
+    n = len(g.data)
+    R, F = g.nrecords, g.nrecords * g.ncols
+    dev = torch.device("cuda:0")
+    d_in = torch.from_numpy(g.data).to(dev)
+    out = pp.alloc_outputs(types, R, F, device=dev)
+    ws = torch.empty(pp.workspace_size(n), dtype=torch.uint8, device=dev)
+    call = pp.Call(d_in, n, dfa, types, out, ws)
+    stream = torch.cuda.current_stream()
+    steps = max(args.steps, 50)
+    for _ in range(max(args.warmup, 5)):
+        call.launch(stream)
+    torch.cuda.synchronize()
+    res = out.result_dict()
+    if res["status"] != pp.RESULT_OK or res["num_records"] != R or res["num_fields"] != F:
+        print(f"[bench] unexpected result {res}", file=sys.stderr)
+        sys.exit(1)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(steps)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        call.launch(stream)
+        b.record(stream)
+        b.synchronize()  # one call at a time: latency, not throughput
+    wall = time.perf_counter() - wall0
+    per = sorted(a.elapsed_time(b) * 1e3 for a, b in evs)  # us
+    med = per[len(per) // 2]
+    outb = output_bytes(R, F, types)
+    line = {
+        "metric": "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency",
+        "value": round(n / (med / 1e6) / 1e9, 3),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": steps,
+        "warmup": max(args.warmup, 5),
+        "ms_per_step": round(wall * 1e3 / steps, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic (seeded RFC-4180-style CSV; no dataset used)",
+        "config": {"workload": "c1: 10,000 records x 8 columns (2 int64, 2 float64, 1 timestamp, 3 strings, "
+                               "20% quoted with embedded commas, LF and doubled quotes), csv4 DFA, one plain launch",
+                   "bytes": n, "records": R, "fields": F},
+        "latency_us": {"p50": round(med, 2), "p10": round(per[len(per) // 10], 2),
+                       "p90": round(per[(9 * len(per)) // 10], 2), "min": round(per[0], 2)},
+        "in_out_gbs": round((n + outb) / (med / 1e6) / 1e9, 2),
+        "output_bytes": outb,
+        "roofline": {"bound": "hbm", "achieved": round((n + outb) / (med / 1e6) / 1e9, 2), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round((n + outb) / (med / 1e6) / 1e9 / HBM_PEAK_GBS, 5),
+                     "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        reps = 20
+        t = time.perf_counter()
+        for _ in range(reps):
+            oracle.parse(g.data, dfa, types, cap_records=R, cap_fields=F)
+        cpu_s = (time.perf_counter() - t) / reps
+        line["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                                "sample": f"the whole {n}-byte workload, {reps} sequential oracle parses "
+                                          f"({cpu_s * 1e3:.2f} ms each)"}
     print(json.dumps(line), flush=True)
 
 

@@ -201,21 +201,56 @@ __device__ inline SV<NS8> sv_from_nib(uint32_t x)
 }
 
 template <bool NS8>
-__device__ inline SV<NS8> shfl_up_sv(SV<NS8> v, int d)
-{
-    SV<NS8> r;
-    r.lo = (uint32_t)__shfl_up((int)v.lo, d);
-    r.hi = NS8 ? (uint32_t)__shfl_up((int)v.hi, d) : 0u;
-    return r;
-}
-
-template <bool NS8>
 __device__ inline SV<NS8> shfl_down_sv(SV<NS8> v, int d)
 {
     SV<NS8> r;
     r.lo = (uint32_t)__shfl_down((int)v.lo, d);
     r.hi = NS8 ? (uint32_t)__shfl_down((int)v.hi, d) : 0u;
     return r;
+}
+
+// ---- wavefront scans through DPP -------------------------------------------------
+// A DPP move reads another lane's register within the same instruction (no LDS
+// round trip). Controls (GFX9 encoding): row_shr:n = 0x110 + n within rows of
+// 16 lanes; row_bcast:15 = 0x142 (lane 15 of each row to the next row, rows
+// 1 and 3 written); row_bcast:31 = 0x143 (lane 31 to rows 2 and 3);
+// wave_shr:1 = 0x138. Lanes whose source is outside the row (or wave), and
+// rows the row mask leaves out, keep `old`, which the scans pass as the
+// operator's identity.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint32_t dpp_move(uint32_t old, uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROWS, 0xF, false);
+}
+
+template <int CTRL, int ROWS, bool NS8>
+__device__ __forceinline__ SV<NS8> dpp_sv(SV<NS8> v)
+{
+    const SV<NS8> id = sv_identity<NS8>();
+    SV<NS8> r;
+    r.lo = dpp_move<CTRL, ROWS>(id.lo, v.lo);
+    r.hi = NS8 ? dpp_move<CTRL, ROWS>(id.hi, v.hi) : 0u;
+    return r;
+}
+
+// Inclusive composition scan over the lanes (lane order = chunk order).
+template <bool NS8>
+__device__ __forceinline__ SV<NS8> wave_scan_sv(SV<NS8> x)
+{
+    x = compose(dpp_sv<0x111, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x112, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x114, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x118, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x142, 0xA, NS8>(x), x);
+    x = compose(dpp_sv<0x143, 0xC, NS8>(x), x);
+    return x;
+}
+
+// The previous lane's value (identity in lane 0).
+template <bool NS8>
+__device__ __forceinline__ SV<NS8> wave_prev_sv(SV<NS8> x)
+{
+    return dpp_sv<0x138, 0xF, NS8>(x);
 }
 
 // One DFA step through the combined table: state*8 -> next state*8.
@@ -246,10 +281,23 @@ __device__ inline Cnt cnt_combine(Cnt a, Cnt b)
     return r;
 }
 
-__device__ inline Cnt shfl_up_cnt(Cnt c, int d)
+template <int CTRL, int ROWS>
+__device__ __forceinline__ Cnt dpp_cnt(Cnt c)
 {
-    return {(uint32_t)__shfl_up((int)c.nr, d), (uint32_t)__shfl_up((int)c.nf, d),
-            (uint32_t)__shfl_up((int)c.col, d), (uint32_t)__shfl_up((int)c.last, d)};
+    return {dpp_move<CTRL, ROWS>(0u, c.nr), dpp_move<CTRL, ROWS>(0u, c.nf), dpp_move<CTRL, ROWS>(0u, c.col),
+            dpp_move<CTRL, ROWS>(0u, c.last)};
+}
+
+// Inclusive scan of the count elements over the lanes (identity: all zero).
+__device__ __forceinline__ Cnt wave_scan_cnt(Cnt x)
+{
+    x = cnt_combine(dpp_cnt<0x111, 0xF>(x), x);
+    x = cnt_combine(dpp_cnt<0x112, 0xF>(x), x);
+    x = cnt_combine(dpp_cnt<0x114, 0xF>(x), x);
+    x = cnt_combine(dpp_cnt<0x118, 0xF>(x), x);
+    x = cnt_combine(dpp_cnt<0x142, 0xA>(x), x);
+    x = cnt_combine(dpp_cnt<0x143, 0xC>(x), x);
+    return x;
 }
 
 // ---- device-wide count prefix ------------------------------------------------------
@@ -302,12 +350,6 @@ struct ByteSrc {
         return r >= 0 ? lds[r] : gptr(g)[pos];
     }
 };
-
-__device__ inline int64_t wave_sum(int64_t v)
-{
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d);
-    return v;
-}
 
 // The general conversions (any length, any position, exponents, more than
 // 19 digits). Returns 1 converted, 0 not a value of the type. (Kept inline:
@@ -545,19 +587,12 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
 
     // ---- 3. composition scan ------------------------------------------------------------
-    SV<NS8> incl = vec;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        SV<NS8> y = shfl_up_sv(incl, d);
-        if (lane >= d) incl = compose(y, incl);
-    }
+    const SV<NS8> incl = wave_scan_sv<NS8>(vec);
     if (lane == 63) s_wsv[wave] = incl;
     __syncthreads();
     SV<NS8> wpre = sv_identity<NS8>();
     for (int w = 0; w < wave; ++w) wpre = compose(wpre, s_wsv[w]);
-    SV<NS8> ex = shfl_up_sv(incl, 1);
-    if (lane == 0) ex = sv_identity<NS8>();
-    ex = compose(wpre, ex);  // exclusive prefix of this chunk within the tile
+    const SV<NS8> ex = compose(wpre, wave_prev_sv<NS8>(incl));  // exclusive prefix of this chunk within the tile
 
     if (wave == 0) {
         SV<NS8> agg = sv_identity<NS8>();
@@ -687,20 +722,13 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
 
     // ---- 5. count scans ------------------------------------------------------------------
-    Cnt cin = mine;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        Cnt y = shfl_up_cnt(cin, d);
-        if (lane >= d) cin = cnt_combine(y, cin);
-    }
+    const Cnt cin = wave_scan_cnt(mine);
     if (lane == 63) s_wcnt[wave] = cin;
     if (mine.nf) atomicMax(&s_lasttid, tid);
     __syncthreads();
     Cnt cpre = {0u, 0u, 0u, 0u};
     for (int w = 0; w < wave; ++w) cpre = cnt_combine(cpre, s_wcnt[w]);
-    Cnt cex = shfl_up_cnt(cin, 1);
-    if (lane == 0) cex = {0u, 0u, 0u, 0u};
-    cex = cnt_combine(cpre, cex);
+    const Cnt cex = cnt_combine(cpre, dpp_cnt<0x138, 0xF>(cin));  // previous lane's (zero in lane 0)
     Cnt tagg = {0u, 0u, 0u, 0u};
     for (int w = 0; w < NW; ++w) tagg = cnt_combine(tagg, s_wcnt[w]);
 
@@ -1035,12 +1063,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         }
     }
 
-    nerr = wave_sum(nerr);
-    nragged = wave_sum(nragged);
-    if (lane == 0 && (nerr | nragged)) {
-        atomicAdd(&s_err, (u64)nerr);
-        atomicAdd(&s_ragged, (u64)nragged);
-    }
+    if (nerr) atomicAdd(&s_err, (u64)nerr);
+    if (nragged) atomicAdd(&s_ragged, (u64)nragged);
     __syncthreads();
     if (tid == 0) {
         if (s_err) atomicAdd((u64*)&p.result->num_conversion_errors, s_err);  // rare: generic is fine
