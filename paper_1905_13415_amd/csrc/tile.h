@@ -594,14 +594,52 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     for (int w = 0; w < wave; ++w) wpre = compose(wpre, s_wsv[w]);
     const SV<NS8> ex = compose(wpre, wave_prev_sv<NS8>(incl));  // exclusive prefix of this chunk within the tile
 
+    // the tile's aggregate goes out first; successors wait on it
+    SV<NS8> agg = sv_identity<NS8>();
     if (wave == 0) {
-        SV<NS8> agg = sv_identity<NS8>();
         for (int w = 0; w < NW; ++w) agg = compose(agg, s_wsv[w]);
-        SV<NS8> pre = sv_identity<NS8>();
-        if (tile == 0) {
-            if (lane == 0) publish(tw + W_STATE, kIncl | sv_to_nib(agg));
+        if (lane == 0) publish(tw + W_STATE, (tile == 0 ? kIncl : kAgg) | sv_to_nib(agg));
+    }
+
+    // ---- 4. tag pass ----------------------------------------------------------------------
+    // x = tcomb[b] >> (8*state): bits 3-5 next state * 8, bit 6 tag bit 0, bit 7 tag bit 1.
+    // It runs first under a guess, the tile starting in the DFA's start state,
+    // while the state lookback is still to come; chunks whose start state the
+    // lookback then changes run it again.
+    M p0 = 0, p1 = 0;
+    uint32_t s8 = 0;
+    auto tag_pass = [&](const uint32_t s_init) {
+        p0 = 0;
+        p1 = 0;
+        s8 = s_init * 8u;
+        auto tstep = [&](int i) {
+            const uint32_t b = byte_at(i);
+            uint32_t x;
+            if constexpr (NS8) {
+                const uint32_t e = s_tcomb[2 * b + (s8 >> 5)];
+                x = __builtin_amdgcn_ubfe(e, s8 & 31u, 8);
+            } else {
+                x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
+            }
+            s8 = x & 0x38u;
+            p0 |= (M)((x >> 6) & 1u) << i;
+            p1 |= (M)(x >> 7) << i;
+        };
+        if (len == B) {
+#pragma unroll
+            for (int i = 0; i < B; ++i) tstep(i);
         } else {
-            if (lane == 0) publish(tw + W_STATE, kAgg | sv_to_nib(agg));
+#pragma unroll
+            for (int i = 0; i < B; ++i)
+                if (i < len) tstep(i);
+        }
+    };
+    const uint32_t s_guess = sv_get(ex, (uint32_t)p.start_state);
+    tag_pass(s_guess);
+
+    if (wave == 0) {
+        SV<NS8> pre = sv_identity<NS8>();
+        if (tile > 0) {
             // one wavefront polls 64 predecessors per step
             SV<NS8> acc = sv_identity<NS8>();
             for (int64_t base = (int64_t)tile - 1;; base -= 64) {
@@ -640,32 +678,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
     const uint32_t s_start = sv_get(ex, s_s0);
-
-    // ---- 4. tag pass ----------------------------------------------------------------------
-    // x = tcomb[b] >> (8*state): bits 3-5 next state * 8, bit 6 tag bit 0, bit 7 tag bit 1.
-    M p0 = 0, p1 = 0;
-    uint32_t s8 = s_start * 8u;
-    auto tstep = [&](int i) {
-        const uint32_t b = byte_at(i);
-        uint32_t x;
-        if constexpr (NS8) {
-            const uint32_t e = s_tcomb[2 * b + (s8 >> 5)];
-            x = __builtin_amdgcn_ubfe(e, s8 & 31u, 8);
-        } else {
-            x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
-        }
-        s8 = x & 0x38u;
-        p0 |= (M)((x >> 6) & 1u) << i;
-        p1 |= (M)(x >> 7) << i;
-    };
-    if (len == B) {
-#pragma unroll
-        for (int i = 0; i < B; ++i) tstep(i);
-    } else {
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-            if (i < len) tstep(i);
-    }
+    if (s_start != s_guess) tag_pass(s_start);
     const uint32_t s_end = s8 >> 3;
     const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
     const int64_t cstart = tile_start + c0;
