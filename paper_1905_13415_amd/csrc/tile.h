@@ -478,7 +478,6 @@ struct TileSmem {
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
     uint32_t anyctl, s0, fin, last_sa, ctl_last;
-    int lasttid;
     u64 pref[4];
     u64 err, ragged;
 };
@@ -512,7 +511,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     uint32_t& s_final = sm.fin;
     uint32_t& s_last_sa = sm.last_sa;
     uint32_t& s_ctl_last = sm.ctl_last;
-    int& s_lasttid = sm.lasttid;
     u64* const s_pref = sm.pref;
     u64& s_err = sm.err;
     u64& s_ragged = sm.ragged;
@@ -523,7 +521,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 
     __syncthreads();  // the previous tile of this workgroup is done with LDS
     if (tid == 0) {
-        s_lasttid = -1;
         s_anyctl = 0;
         s_err = 0;
         s_ragged = 0;
@@ -737,7 +734,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     // ---- 5. count scans ------------------------------------------------------------------
     const Cnt cin = wave_scan_cnt(mine);
     if (lane == 63) s_wcnt[wave] = cin;
-    if (mine.nf) atomicMax(&s_lasttid, tid);
     __syncthreads();
     Cnt cpre = {0u, 0u, 0u, 0u};
     for (int w = 0; w < wave; ++w) cpre = cnt_combine(cpre, s_wcnt[w]);
@@ -745,8 +741,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     Cnt tagg = {0u, 0u, 0u, 0u};
     for (int w = 0; w < NW; ++w) tagg = cnt_combine(tagg, s_wcnt[w]);
 
-    // state after the tile's last delimiter, from the chunk that holds it
-    if (tid == s_lasttid) {
+    // state after the tile's last delimiter, from the chunk that holds it (the
+    // one whose own last delimiter is the tile's: positions are unique)
+    if (mine.nf && mine.last == tagg.last) {
         uint32_t sa = 0;
         if (!vend) {
             const int hb = msb(dmask);
