@@ -719,7 +719,10 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         mine.col = popc(dmask);
     }
     mine.last = vend ? (uint32_t)(tile_len + 1) : (dmask ? (uint32_t)(c0 + msb(dmask) + 1) : 0u);
-    if (cmask) s_anyctl = 1u;
+    {
+        const bool wave_ctl = ballot(cmask != 0) != 0;  // every lane takes part in the ballot
+        if (lane == 0 && wave_ctl) s_anyctl = 1u;       // one store per wavefront
+    }
     if constexpr (B == 64) {
         s_ctl[2 * tid] = (uint32_t)cmask;
         s_ctl[2 * tid + 1] = (uint32_t)(cmask >> 32);
