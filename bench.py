@@ -88,8 +88,8 @@ def main():
                     help="upper bound of the c4 buffer sizes (8 MiB gives the ~4 GB variant)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU; --gpus {args.gpus} is not supported "
-              f"(the parse shards by byte range with one small all-gather; see DESIGN.md)",
+        print(f"bench.py: measures one GPU; --gpus {args.gpus} is not supported "
+              f"(across GPUs the parse would shard by byte range with one small all-gather)",
               file=sys.stderr)
         sys.exit(2)
     if args.workload == "c1":

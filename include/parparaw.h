@@ -43,7 +43,7 @@ typedef int32_t pp_status_t;
 #define PP_ERR_SCHEMA (-3)      /* too many columns or unknown type */
 #define PP_ERR_WORKSPACE (-4)   /* workspace smaller than pp_workspace_size() */
 #define PP_ERR_HIP (-5)         /* a HIP launch failed */
-#define PP_ERR_UNSUPPORTED (-6) /* a combination this build does not support */
+#define PP_ERR_UNSUPPORTED (-6) /* a size or combination the library does not support */
 #define PP_ERR_BUDGET (-7)      /* a request larger than the server's whole device budget */
 
 /* Symbol tags (Sec. 3.1: record delimiter, field delimiter, control symbol,
