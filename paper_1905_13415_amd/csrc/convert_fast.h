@@ -127,7 +127,8 @@ __device__ __forceinline__ int ser_int64(const Win& x, int len, int64_t* out)
 // larger than the final one, so while the final value is below 2^53 each
 // step v*10+d is exact; a larger final value is caught by the range check
 // (rounding is monotonic, so it cannot land below 2^53).
-__device__ __forceinline__ int ser_float64(const Win& x, int len, double* out)
+// pow10: 10^k for 0 <= k <= 22 (a table the caller keeps in LDS).
+__device__ __forceinline__ int ser_float64(const Win& x, int len, double* out, const double* pow10)
 {
     const uint32_t c0 = x.at(0);
     const bool neg = c0 == '-';
@@ -163,7 +164,7 @@ __device__ __forceinline__ int ser_float64(const Win& x, int len, double* out)
     }
     const int frac = ndot ? len - 1 - (31 - __clz((int)dots)) : 0;
     if (!(v < 9007199254740992.0) || frac > 22) return -1;
-    if (frac) v = v / exact_pow10(frac);
+    if (frac) v = v / pow10[frac];
     *out = neg ? -v : v;
     return 1;
 }

@@ -475,6 +475,7 @@ struct TileSmem {
     // column outputs offset to this tile's first record, as separate arrays of
     // 8-byte entries (cheap 32-bit LDS indexing)
     u64 cbv[PP_MAX_COLUMNS], cbm[PP_MAX_COLUMNS], cbe[PP_MAX_COLUMNS];
+    double pow10[24];  // 10^k, k <= 22, for the decimal conversions
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
     uint32_t anyctl, s0, fin, last_sa, ctl_last;
@@ -525,6 +526,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         s_err = 0;
         s_ragged = 0;
     }
+    if (tid <= 22) sm.pow10[tid] = exact_pow10(tid);
     // per-byte transition rows, precomputed by parse_init from the group table
     for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
         s_tnext[k] = gptr(p.tables)[k];
@@ -1009,7 +1011,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                         const Win x = load_win_lazy(words, bb, len);
                         if (ty == PP_FLOAT64) {
                             double dv = 0.0;
-                            r = ser_float64(x, len, &dv);
+                            r = ser_float64(x, len, &dv, sm.pow10);
                             bits = __builtin_bit_cast(u64, dv);
                         } else {
                             int64_t iv = 0;
