@@ -84,6 +84,7 @@ def main():
     ap.add_argument("--c5-pool-bytes", type=int, default=1 << 30,
                     help="size of the pinned log text that c5 requests are cut from")
     ap.add_argument("--c5-budget", type=int, default=32 << 30, help="server device budget, bytes")
+    ap.add_argument("--c5-copy-streams", type=int, default=4, help="server host-to-device copy streams")
     ap.add_argument("--c4-max-bytes", type=int, default=64 << 20,
                     help="upper bound of the c4 buffer sizes (8 MiB gives the ~4 GB variant)")
     args = ap.parse_args()
@@ -571,7 +572,8 @@ def bench_c5(args):
         if serial:
             srv = pp.Server([dfa], args.c5_budget, max_slots=1, copy_streams=1, compute_streams=1)
         else:
-            srv = pp.Server([dfa], args.c5_budget, max_slots=256, copy_streams=2, compute_streams=2)
+            srv = pp.Server([dfa], args.c5_budget, max_slots=256, copy_streams=args.c5_copy_streams,
+                            compute_streams=2)
         lat, first, last = [], None, 0
         i = done = 0
         base = time.monotonic_ns() + 2_000_000
@@ -627,7 +629,7 @@ def bench_c5(args):
         "config": {
             "workload": f"c5: {N} requests cut from a {len(data)}-byte pinned log text, sizes log-uniform in "
                         "[4 KiB, 256 MiB], log6 DFA, 12 columns, request loop with continuous batching",
-            "bytes": total, "budget_bytes": args.c5_budget,
+            "bytes": total, "budget_bytes": args.c5_budget, "copy_streams": args.c5_copy_streams,
         },
         "saturated": {"overlapped": closed, "serial": closed_serial},
         "serial_service_ms": round(service_ns / 1e6, 4),

@@ -240,7 +240,7 @@ typedef struct pp_server pp_server_t;
 typedef struct {
     size_t hbm_budget_bytes; /* device memory the server holds (>= 64 MiB) */
     int32_t max_slots;       /* admitted and not yet released requests, at most (>= 1) */
-    int32_t copy_streams;    /* 1..4 host-to-device copy streams (0: 2) */
+    int32_t copy_streams;    /* 1..4 host-to-device copy streams (0: 4) */
     int32_t compute_streams; /* 1..2 streams running batched launches (0: 2) */
     int32_t max_batch;       /* requests per batched launch (0: max_slots) */
     pp_options_t opts;       /* launch shape (zeros: default) */

@@ -454,7 +454,7 @@ class Server:
     """Request loop over pinned host inputs (pp_server_*). ``dfas`` are the
     dialects requests refer to by index."""
 
-    def __init__(self, dfas, hbm_budget_bytes: int, max_slots: int = 64, copy_streams: int = 2,
+    def __init__(self, dfas, hbm_budget_bytes: int, max_slots: int = 64, copy_streams: int = 4,
                  compute_streams: int = 2, max_batch: int = 0, opts: Optional[PpOptions] = None):
         self._dfas = (PpDfa * len(dfas))(*[dfa_struct(d) for d in dfas])
         cfg = PpServerConfig(hbm_budget_bytes, max_slots, copy_streams, compute_streams, max_batch,

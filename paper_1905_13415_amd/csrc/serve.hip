@@ -296,7 +296,7 @@ extern "C" pp_status_t pp_server_create(const pp_server_config_t* cfg, const pp_
     if (!cfg || !out || !dfas || ndfas < 1) return PP_ERR_ARG;
     *out = nullptr;
     pp_server_config_t c = *cfg;
-    if (c.copy_streams == 0) c.copy_streams = 2;
+    if (c.copy_streams == 0) c.copy_streams = 4;  // several small copies in flight hide each one's setup
     if (c.compute_streams == 0) c.compute_streams = 2;
     if (c.max_slots <= 0 || c.copy_streams < 1 || c.copy_streams > kMaxCopyStreams || c.compute_streams < 1 ||
         c.compute_streams > kMaxComputeStreams || c.max_batch < 0 || c.hbm_budget_bytes < (64u << 20))
