@@ -70,13 +70,6 @@ __device__ __forceinline__ const PP_GLOBAL T* gptr(const T* ptr)
     return (const PP_GLOBAL T*)ptr;
 }
 
-// Output pointers of one column, as seen from a tile's first record.
-struct ColBase {
-    void* values;
-    uint8_t* valid;
-    int64_t* str_end;
-};
-
 // Everything one tile needs about its buffer, dialect and outputs.
 struct TileArgs {
     const uint8_t* in;
@@ -138,8 +131,10 @@ __device__ inline u64 shfl_down64(u64 v, int d)
 
 __device__ inline u64 readlane0_64(u64 v)
 {
-    uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
-    uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    // the builtin returns a signed int: take each half as unsigned before
+    // widening, or a low half with bit 31 set would sign-extend over the high
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)(v >> 32));
     return ((u64)hi << 32) | lo;
 }
 
@@ -931,24 +926,32 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         }
 
         // ---- 7. typed columns ---------------------------------------------------------------
-        // A thread takes one record of the tile (the records it closes, plus
-        // the open one) and a contiguous group of its columns; lanes of a
-        // wavefront hold consecutive records of the same group, so at every
-        // step they convert the same column (one type, no divergence) and
-        // their stores into that typed column are contiguous. Walking a
-        // group's fields in order reads one delimiter position per field.
+        // The records of the tile (those it closes, plus the open one) are cut
+        // into blocks of 64 and the columns into contiguous groups; a
+        // wavefront takes one (group, record block) pair at a time, a lane
+        // one record of the block, and walks the group's columns in order.
+        // The column is thus the same for every lane by construction: its
+        // type and output bases are wavefront-uniform (scalar branches, no
+        // divergence on the type), and the stores into a typed column are
+        // contiguous. Walking a group's fields in order reads one delimiter
+        // position per field.
         const uint32_t nrec = (uint32_t)Rt + 1u;  // records closed here plus the open one
         const int64_t roomr = p.cap_records - R0;
         const uint32_t lr_cap = roomr <= 0 ? 0u : (roomr > (int64_t)nrec ? nrec : (uint32_t)roomr);
         const bool anyctl = s_anyctl != 0;
         const uint32_t* const words = reinterpret_cast<const uint32_t*>(s_bytes);
-        uint32_t groups = (uint32_t)NT / nrec;
+        const uint32_t nrb = (nrec + 63u) >> 6;  // record blocks
+        uint32_t groups = (uint32_t)NW / nrb;
         groups = groups < 1u ? 1u : (groups > (uint32_t)ncols ? (uint32_t)ncols : groups);
         const uint32_t per = ncols ? ((uint32_t)ncols + groups - 1u) / groups : 0u;  // columns per group
         groups = per ? ((uint32_t)ncols + per - 1u) / per : 0u;
-        const uint32_t work = nrec * groups;
-        for (uint32_t w = tid; w < work; w += NT) {
-            const uint32_t g = w / nrec, lr = w - g * nrec;
+        const uint32_t witems = nrb * groups;
+        // the wavefront's index as a scalar (every lane is active here)
+        const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)wave);
+        for (uint32_t wi = wv; wi < witems; wi += (uint32_t)NW) {
+            const uint32_t g = wi / nrb, rb = wi - g * nrb;
+            const uint32_t lr = rb * 64u + (uint32_t)lane;
+            if (lr >= nrec) continue;  // idle lanes of the group's last record block
             const uint32_t first = lr ? s_recend[lr - 1] + 1u : 0u;
             const uint32_t end1 = lr < (uint32_t)Rt ? s_recend[lr] + 1u : (uint32_t)Ft;  // one past the last field
             // the open record from the previous tile continues at column C0 (any
@@ -960,15 +963,19 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const bool st = lr < lr_cap;
             int pend = -1;  // position of the delimiter before the next field, once known
             for (uint32_t c = cb; c < ce; ++c) {
+                // Column c's type and bases, read while lane 0 of the block
+                // (record rb*64 < nrec) is active, as scalars.
+                const uint32_t ty = __builtin_amdgcn_readfirstlane((uint32_t)s_cols[c].type);
+                u64* const vals = (u64*)readlane0_64(s_cbv[c]);
+                uint8_t* const valid = (uint8_t*)readlane0_64(s_cbm[c]);
+                int64_t* const ends = (int64_t*)readlane0_64(s_cbe[c]);
                 if (c < cf) continue;
                 const uint32_t L = first + c - cf;
-                const uint32_t ty = s_cols[c].type;
                 if (L >= end1) {
                     if (lr < (uint32_t)Rt && st && ty != PP_SKIP) {  // missing column of a short record
-                        const ColBase cd = {(void*)s_cbv[c], (uint8_t*)s_cbm[c], (int64_t*)s_cbe[c]};
-                        gptr((u64*)cd.values)[lr] = 0;
-                        gptr(cd.valid)[lr] = 0;
-                        if (ty == PP_STRING) gptr(cd.str_end)[lr] = 0;
+                        gptr(vals)[lr] = 0;
+                        gptr(valid)[lr] = 0;
+                        if (ty == PP_STRING) gptr(ends)[lr] = 0;
                     }
                     continue;
                 }
@@ -991,17 +998,16 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
                     if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
                 }
-                const ColBase cd = {(void*)s_cbv[c], (uint8_t*)s_cbm[c], (int64_t*)s_cbe[c]};
                 if (ty == PP_STRING) {
                     if (st) {
-                        gptr((int64_t*)cd.values)[lr] = tile_start + bb;
-                        gptr(cd.str_end)[lr] = tile_start + ee;
-                        gptr(cd.valid)[lr] = 1;
+                        gptr((int64_t*)vals)[lr] = tile_start + bb;
+                        gptr(ends)[lr] = tile_start + ee;
+                        gptr(valid)[lr] = 1;
                     }
                 } else if (ee == bb) {  // empty: the column default, not an error
                     if (st) {
-                        gptr((u64*)cd.values)[lr] = 0;
-                        gptr(cd.valid)[lr] = 0;
+                        gptr(vals)[lr] = 0;
+                        gptr(valid)[lr] = 0;
                     }
                 } else {
                     const int len = ee - bb;
@@ -1024,8 +1030,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     if (r < 0) r = convert_general((int)ty, src, tile_start + bb, tile_start + ee, &bits);
                     nerr += r == 0;
                     if (st) {
-                        gptr((u64*)cd.values)[lr] = r ? bits : 0ull;
-                        gptr(cd.valid)[lr] = (uint8_t)r;
+                        gptr(vals)[lr] = r ? bits : 0ull;
+                        gptr(valid)[lr] = (uint8_t)r;
                     }
                 }
             }
