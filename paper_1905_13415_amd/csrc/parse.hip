@@ -34,8 +34,9 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     __shared__ TileSmem<NT, B> sm;
     __shared__ uint32_t s_ticket;
     if (threadIdx.x == 0) s_ticket = atomicAdd(p.counter, 1u);
+    tile_setup<NT, B, NS8>(p.a, sm);  // in flight together with the ticket
     __syncthreads();
-    parse_tile<NT, B, NS8>(p.a, s_ticket, sm);
+    parse_tile<NT, B, NS8, false>(p.a, s_ticket, sm);
 }
 
 // Resets the workspace and the result before a parse; writes the outputs of

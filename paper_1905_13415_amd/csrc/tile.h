@@ -478,8 +478,25 @@ struct TileSmem {
     u64 err, ragged;
 };
 
-// The whole pipeline for tile `tile` of one buffer (steps 1-7 above).
+// A buffer's constants in LDS: the per-byte transition rows (built by the
+// init kernel from the DFA's group table), the column descriptors and the
+// powers of ten. Visible after the workgroup's next barrier.
 template <int NT, int B, bool NS8>
+__device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& sm)
+{
+    const int tid = threadIdx.x;
+    if (tid <= 22) sm.pow10[tid] = exact_pow10(tid);
+    for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
+        sm.tnext[k] = gptr(p.tables)[k];
+        sm.tcomb[k] = gptr(p.tables)[512 + k];
+    }
+    for (int c = tid; c < p.ncols; c += NT) sm.cols[c] = p.cols[c];
+}
+
+// The whole pipeline for tile `tile` of one buffer (steps 1-7 above).
+// SETUP: load the buffer's constants here (else the caller has, before a
+// barrier that precedes this call).
+template <int NT, int B, bool NS8, bool SETUP = true>
 __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t tile, TileSmem<NT, B>& sm)
 {
     static_assert(B == 16 || B == 32 || B == 64, "chunk bitmaps are one or two dwords");
@@ -521,14 +538,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         s_err = 0;
         s_ragged = 0;
     }
-    if (tid <= 22) sm.pow10[tid] = exact_pow10(tid);
-    // per-byte transition rows, precomputed by parse_init from the group table
-    for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
-        s_tnext[k] = gptr(p.tables)[k];
-        s_tcomb[k] = gptr(p.tables)[512 + k];
-    }
-    for (int c = tid; c < p.ncols; c += NT) s_cols[c] = p.cols[c];
-    __syncthreads();
+    if constexpr (SETUP) tile_setup<NT, B, NS8>(p, sm);  // first read after the staging barrier
 
     const int64_t n = p.n;
     const int64_t tile_start = (int64_t)tile * TILE;
@@ -615,7 +625,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             } else {
                 x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
             }
-            s8 = x & 0x38u;
+            // <= 4 states: the next state * 8 sits in bits 3-4 and the bit-field
+            // offset reads bits 0-4 only, so x serves as the offset unmasked
+            s8 = NS8 ? (x & 0x38u) : x;
             p0 |= (M)((x >> 6) & 1u) << i;
             p1 |= (M)(x >> 7) << i;
         };
@@ -673,7 +685,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     __syncthreads();
     const uint32_t s_start = sv_get(ex, s_s0);
     if (s_start != s_guess) tag_pass(s_start);
-    const uint32_t s_end = s8 >> 3;
+    const uint32_t s_end = (s8 & 0x38u) >> 3;
     const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
     const int64_t cstart = tile_start + c0;
     const bool holds_last = len > 0 && cstart + len == n;
