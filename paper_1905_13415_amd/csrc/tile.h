@@ -571,6 +571,11 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         }
     }
     auto byte_at = [&](int i) -> uint32_t { return (wd[i >> 2] >> ((i & 3) * 8)) & 0xffu; };
+    // Cold paths (a chunk shorter than B, a second tag pass, the searches
+    // below) walk the chunk in rolled loops over its LDS copy: the unrolled
+    // forms would add kilobytes of code that every tile's hot path shares
+    // the instruction cache with.
+    const uint8_t* const cb_lds = s_bytes + c0;
 
     // ---- 2. multi-state pass ----------------------------------------------------------
     SV<NS8> vec = sv_identity<NS8>();
@@ -585,9 +590,13 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 #pragma unroll
         for (int i = 0; i < B; ++i) mstep(i);
     } else {
-#pragma unroll
-        for (int i = 0; i < B; ++i)
-            if (i < len) mstep(i);
+        for (int i = 0; i < len; ++i) {
+            const uint32_t b = cb_lds[i];
+            SV<NS8> t;
+            if constexpr (NS8) { t.lo = s_tnext[2 * b]; t.hi = s_tnext[2 * b + 1]; }
+            else { t.lo = s_tnext[b]; t.hi = 0; }
+            vec = compose(vec, t);
+        }
     }
 
     // ---- 3. composition scan ------------------------------------------------------------
@@ -612,12 +621,11 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     // lookback then changes run it again.
     M p0 = 0, p1 = 0;
     uint32_t s8 = 0;
-    auto tag_pass = [&](const uint32_t s_init) {
+    auto tag_pass = [&](const uint32_t s_init, const bool hot) {
         p0 = 0;
         p1 = 0;
         s8 = s_init * 8u;
-        auto tstep = [&](int i) {
-            const uint32_t b = byte_at(i);
+        auto tstep = [&](int i, uint32_t b) {
             uint32_t x;
             if constexpr (NS8) {
                 const uint32_t e = s_tcomb[2 * b + (s8 >> 5)];
@@ -631,17 +639,15 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             p0 |= (M)((x >> 6) & 1u) << i;
             p1 |= (M)(x >> 7) << i;
         };
-        if (len == B) {
+        if (hot && len == B) {
 #pragma unroll
-            for (int i = 0; i < B; ++i) tstep(i);
+            for (int i = 0; i < B; ++i) tstep(i, byte_at(i));
         } else {
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-                if (i < len) tstep(i);
+            for (int i = 0; i < len; ++i) tstep(i, cb_lds[i]);
         }
     };
     const uint32_t s_guess = sv_get(ex, (uint32_t)p.start_state);
-    tag_pass(s_guess);
+    tag_pass(s_guess, true);
 
     if (wave == 0) {
         SV<NS8> pre = sv_identity<NS8>();
@@ -684,7 +690,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
     const uint32_t s_start = sv_get(ex, s_s0);
-    if (s_start != s_guess) tag_pass(s_start);
+    if (s_start != s_guess) tag_pass(s_start, false);  // rare: the rolled form
     const uint32_t s_end = (s8 & 0x38u) >> 3;
     const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
     const int64_t cstart = tile_start + c0;
@@ -696,12 +702,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         const uint32_t inv8 = (uint32_t)p.invalid_state * 8u;
         uint32_t r8 = s_start * 8u;
         int at = -1;
-#pragma unroll
-        for (int i = 0; i < B; ++i) {
-            if (i < len && at < 0) {
-                r8 = step_state<NS8>(s_tcomb, byte_at(i), r8);
-                if (r8 == inv8) at = i;
-            }
+        for (int i = 0; i < len && at < 0; ++i) {
+            r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
+            if (r8 == inv8) at = i;
         }
         gptr(p.result)->first_invalid_offset = cstart + at;
     }
@@ -760,9 +763,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         if (!vend) {
             const int hb = msb(dmask);
             uint32_t r8 = s_start * 8u;
-#pragma unroll
-            for (int i = 0; i < B; ++i)
-                if (i <= hb) r8 = step_state<NS8>(s_tcomb, byte_at(i), r8);
+            for (int i = 0; i <= hb; ++i) r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
             sa = r8 >> 3;
         }
         s_last_sa = sa;
