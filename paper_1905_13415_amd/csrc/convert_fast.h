@@ -3,8 +3,8 @@
 // A field of at most kWin bytes that lies inside the tile is fetched with
 // independent aligned LDS reads and funnel-shifted into registers, so the
 // parse below has no dependent memory accesses and only compile-time byte
-// indices (no scratch). Numbers are parsed SIMD-within-a-register. Each
-// function returns 1 (converted), 0 (not a value of the type: a conversion
+// indices (no scratch). Numbers are parsed byte-serially with selects, dates
+// and times at fixed positions. Each function returns 1 (converted), 0 (not a value of the type: a conversion
 // error) or -1 (defer to the general conversions in convert.h, e.g. more than
 // 19 significant digits or an exponent). The grammar and results are exactly
 // those of convert.h.
@@ -22,38 +22,6 @@ struct Win {
     uint32_t w[kWin / 4];
     __device__ __forceinline__ uint32_t at(int i) const { return (w[i >> 2] >> ((i & 3) * 8)) & 0xffu; }
 };
-
-// Bytes [off, off + kWin) of an LDS byte array of `size` bytes (dword
-// aligned); bytes outside [0, size) read as zero. off may be negative.
-__device__ __forceinline__ Win load_win(const uint32_t* lds_words, int size, int off)
-{
-    const int d0 = off >> 2;  // floor division, also for negative off
-    const uint32_t sh = (uint32_t)(off & 3);
-    const int nw = size >> 2;
-    uint32_t raw[kWin / 4 + 1];
-#pragma unroll
-    for (int k = 0; k <= kWin / 4; ++k)
-        raw[k] = (d0 + k >= 0 && d0 + k < nw) ? lds_words[d0 + k] : 0u;
-    Win r;
-#pragma unroll
-    for (int k = 0; k < kWin / 4; ++k) r.w[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], sh);
-    return r;
-}
-
-// Bytes [off, off + kWin) of an LDS buffer padded so that the read never
-// leaves it (off >= 0).
-__device__ __forceinline__ Win load_win_padded(const uint32_t* lds_words, int off)
-{
-    const int d0 = off >> 2;
-    const uint32_t sh = (uint32_t)(off & 3);
-    uint32_t raw[kWin / 4 + 1];
-#pragma unroll
-    for (int k = 0; k <= kWin / 4; ++k) raw[k] = lds_words[d0 + k];
-    Win r;
-#pragma unroll
-    for (int k = 0; k < kWin / 4; ++k) r.w[k] = __builtin_amdgcn_alignbyte(raw[k + 1], raw[k], sh);
-    return r;
-}
 
 // Bytes [off, off + kWin) of a padded LDS buffer, fetched in two steps: the
 // first 8 bytes always, the rest only when a lane of the wavefront has a
@@ -165,150 +133,6 @@ __device__ __forceinline__ int ser_float64(const Win& x, int len, double* out, c
     const int frac = ndot ? len - 1 - (31 - __clz((int)dots)) : 0;
     if (!(v < 9007199254740992.0) || frac > 22) return -1;
     if (frac) v = v / pow10[frac];
-    *out = neg ? -v : v;
-    return 1;
-}
-
-// ---- SWAR decimal parsing over a right-aligned window -------------------------
-// The field's last byte sits at window byte 23. Bytes before the digits (the
-// sign, and whatever precedes the field) are replaced by '0', the decimal
-// point is removed by moving the bytes before it up by one, and then all 24
-// bytes must be ASCII digits; three 8-byte chunks are converted in parallel.
-
-constexpr uint64_t kOnes = 0x0101010101010101ull, kHigh = 0x8080808080808080ull;
-constexpr uint64_t kZeros = 0x3030303030303030ull;
-
-__device__ __forceinline__ uint64_t low_bytes(int nbytes)  // mask of the lowest nbytes bytes
-{
-    return nbytes <= 0 ? 0ull : nbytes >= 8 ? ~0ull : (1ull << (8 * nbytes)) - 1;
-}
-
-// bit 7 of each byte set iff the byte equals c (exact for the lowest match;
-// only the lowest flagged byte is used)
-__device__ __forceinline__ uint64_t eq_bytes(uint64_t w, uint64_t c)
-{
-    const uint64_t t = w ^ c;
-    return (t - kOnes) & ~t & kHigh;
-}
-
-__device__ __forceinline__ bool all_digits(uint64_t w)
-{
-    return (((w + 0x4646464646464646ull) | (w - kZeros)) & kHigh) == 0;
-}
-
-// value of 8 ASCII digits, the most significant in the lowest byte: pairs
-// (10*d[i] + d[i+1]) fit in a byte; then the four pairs at bytes 0, 2, 4, 6
-// are weighted by 10^6, 10^4, 10^2, 1 with two 64-bit multiplies whose high
-// halves collect the sum.
-__device__ __forceinline__ uint32_t eight_digits(uint64_t w)
-{
-    uint64_t x = w - kZeros;
-    x = x * 10 + (x >> 8);
-    const uint64_t a = (x & 0x000000FF000000FFull) * (100 + (1000000ull << 32));
-    const uint64_t b = ((x >> 16) & 0x000000FF000000FFull) * (1 + (10000ull << 32));
-    return (uint32_t)((a + b) >> 32);
-}
-
-struct Digits {
-    uint64_t w;   // value of the digit string (valid when nsig <= 19)
-    int nsig;     // significant digits (after leading zeros)
-    int frac;     // digits after the decimal point
-    int ndig;     // digits in the field
-    int status;   // 1 ok, 0 not a number, -1 defer
-};
-
-// Right-aligned window of field [end - len, end) -> digit string value.
-__device__ __forceinline__ Digits swar_digits(const Win& x, int len, bool allow_dot)
-{
-    Digits r{0ull, 0, 0, 0, 1};
-    uint64_t W[3];
-#pragma unroll
-    for (int k = 0; k < 3; ++k) W[k] = ((uint64_t)x.w[2 * k + 1] << 32) | x.w[2 * k];
-    const int first = kWin - len;  // window position of the field's first byte
-    // sign of the field
-    uint32_t fb;
-    {
-        const int q = first >> 3, sh = (first & 7) * 8;
-        const uint64_t wq = q == 0 ? W[0] : q == 1 ? W[1] : W[2];
-        fb = (uint32_t)(wq >> sh) & 0xffu;
-    }
-    const bool sign = fb == '+' || fb == '-';
-    const int lead = first + (sign ? 1 : 0);
-#pragma unroll
-    for (int k = 0; k < 3; ++k) {
-        const uint64_t m = low_bytes(lead - 8 * k);
-        W[k] = (W[k] & ~m) | (kZeros & m);
-    }
-    // the first decimal point
-    int p = -1;
-    if (allow_dot) {
-#pragma unroll
-        for (int k = 2; k >= 0; --k) {
-            const uint64_t h = eq_bytes(W[k], 0x2E2E2E2E2E2E2E2Eull);
-            if (h) p = 8 * k + (__builtin_ctzll(h) >> 3);
-        }
-        if (p >= 0) {  // bytes [0, p) move up by one; byte 0 becomes '0'
-            uint64_t prev = 0x30ull << 56;
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                const uint64_t shifted = (W[k] << 8) | (prev >> 56);
-                prev = W[k];
-                const uint64_t m = low_bytes(p + 1 - 8 * k);
-                W[k] = (shifted & m) | (W[k] & ~m);
-            }
-        }
-    }
-    r.ndig = len - (sign ? 1 : 0) - (p >= 0 ? 1 : 0);
-    r.frac = p >= 0 ? kWin - 1 - p : 0;
-    if (!all_digits(W[0]) || !all_digits(W[1]) || !all_digits(W[2])) {
-        r.status = -1;  // exponent, a second point, a stray byte: the general path decides
-        return r;
-    }
-    if (r.ndig == 0) {
-        r.status = 0;
-        return r;
-    }
-    int fnz = kWin;  // first nonzero digit
-#pragma unroll
-    for (int k = 2; k >= 0; --k) {
-        const uint64_t z = W[k] ^ kZeros;
-        const uint64_t nz = (((z & 0x7F7F7F7F7F7F7F7Full) + 0x7F7F7F7F7F7F7F7Full) | z) & kHigh;
-        if (nz) fnz = 8 * k + (__builtin_ctzll(nz) >> 3);
-    }
-    r.nsig = kWin - fnz;
-    if (r.nsig > 19) {
-        r.status = -1;
-        return r;
-    }
-    const uint64_t v0 = fnz < 8 ? eight_digits(W[0]) : 0u;
-    const uint64_t v1 = fnz < 16 ? eight_digits(W[1]) : 0u;
-    const uint64_t v2 = eight_digits(W[2]);
-    r.w = (v0 * 100000000ull + v1) * 100000000ull + v2;
-    return r;
-}
-
-__device__ __forceinline__ int win_int64(const Win& x, int len, bool neg, int64_t* out)
-{
-    const Digits d = swar_digits(x, len, false);
-    if (d.status <= 0) return d.status;
-    if (d.nsig > 18) return -1;  // overflow checks in the general path
-    *out = neg ? -(int64_t)d.w : (int64_t)d.w;
-    return 1;
-}
-
-// Clinger's exact case: <= 19 significant digits, mantissa <= 2^53, at most
-// 22 fraction digits, no exponent.
-__device__ __forceinline__ int win_float64(const Win& x, int len, bool neg, double* out)
-{
-    const Digits d = swar_digits(x, len, true);
-    if (d.status <= 0) return d.status;
-    if (d.w == 0) {
-        *out = neg ? -0.0 : 0.0;
-        return 1;
-    }
-    if (d.w > (1ull << 53) || d.frac > 22) return -1;
-    double v = (double)d.w;
-    if (d.frac) v = v / exact_pow10(d.frac);
     *out = neg ? -v : v;
     return 1;
 }

@@ -393,47 +393,9 @@ __device__ inline int store_field(const TileArgs& p, const ColDesc* cols, const 
         }
         return 0;
     }
-    bool ok;
-    u64 bits;
-    int r = -1;
-    const int64_t off = begin - src.tile_start;
-    const int len = (int)(end - begin);
-    if (off >= 0 && len <= kWin) {  // short field inside the tile: parse from registers
-        const uint32_t* words = reinterpret_cast<const uint32_t*>(src.lds);
-        if (ty == PP_FLOAT64 || ty == PP_INT64) {
-            const Win x = load_win(words, src.tile_size, (int)off + len - kWin);  // right-aligned
-            const bool neg = src.lds[off] == '-';
-            if (ty == PP_FLOAT64) {
-                double dv = 0.0;
-                r = win_float64(x, len, neg, &dv);
-                bits = __builtin_bit_cast(u64, dv);
-            } else {
-                int64_t iv = 0;
-                r = win_int64(x, len, neg, &iv);
-                bits = (u64)iv;
-            }
-        } else {
-            const Win x = load_win(words, src.tile_size, (int)off);
-            int64_t iv = 0;
-            if (ty == PP_TIMESTAMP_S) r = win_timestamp(x, len, &iv);
-            else r = win_date(x, len, &iv);
-            bits = (u64)iv;
-        }
-    }
-    if (r >= 0) {
-        ok = r == 1;
-        if (!ok) bits = 0ull;
-    } else if (ty == PP_FLOAT64) {
-        double dv = 0.0;
-        ok = conv_float64(src, begin, end, &dv);
-        bits = ok ? __builtin_bit_cast(u64, dv) : 0ull;
-    } else {
-        int64_t iv = 0;
-        if (ty == PP_INT64) ok = conv_int64(src, begin, end, &iv);
-        else if (ty == PP_TIMESTAMP_S) ok = conv_timestamp(src, begin, end, &iv);
-        else ok = conv_date(src, begin, end, &iv);
-        bits = ok ? (u64)iv : 0ull;
-    }
+    u64 bits = 0;
+    const bool ok = convert_general(ty, src, begin, end, &bits) == 1;
+    if (!ok) bits = 0ull;
     if (store) {
         gptr((u64*)cd.values)[rec] = bits;
         gptr(cd.valid)[rec] = ok;
@@ -690,7 +652,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
     const uint32_t s_start = sv_get(ex, s_s0);
-    if (s_start != s_guess) tag_pass(s_start, false);  // rare: the rolled form
+    if (__builtin_expect(s_start != s_guess, 0)) tag_pass(s_start, false);  // rare: the rolled form
     const uint32_t s_end = (s8 & 0x38u) >> 3;
     const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
     const int64_t cstart = tile_start + c0;
@@ -984,7 +946,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 int64_t* const ends = (int64_t*)readlane0_64(s_cbe[c]);
                 if (c < cf) continue;
                 const uint32_t L = first + c - cf;
-                if (L >= end1) {
+                if (__builtin_expect(L >= end1, 0)) {
                     if (lr < (uint32_t)Rt && st && ty != PP_SKIP) {  // missing column of a short record
                         gptr(vals)[lr] = 0;
                         gptr(valid)[lr] = 0;
@@ -992,7 +954,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     }
                     continue;
                 }
-                if (L == 0) {  // may begin in an earlier tile: general path
+                if (__builtin_expect(L == 0, 0)) {  // may begin in an earlier tile: general path
                     const int64_t e = tile_start + s_pos[0];
                     pend = s_pos[0];
                     if (ty != PP_SKIP) {
@@ -1040,7 +1002,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                             bits = (u64)iv;
                         }
                     }
-                    if (r < 0) r = convert_general((int)ty, src, tile_start + bb, tile_start + ee, &bits);
+                    if (__builtin_expect(r < 0, 0)) r = convert_general((int)ty, src, tile_start + bb, tile_start + ee, &bits);
                     nerr += r == 0;
                     if (st) {
                         gptr(vals)[lr] = r ? bits : 0ull;
