@@ -70,6 +70,20 @@ __device__ __forceinline__ const PP_GLOBAL T* gptr(const T* ptr)
     return (const PP_GLOBAL T*)ptr;
 }
 
+// Element `idx` of an output array at a 32-bit byte offset from a
+// wavefront-uniform base: the store takes the base in scalar registers and
+// only the offset per lane.
+template <class T>
+__device__ __forceinline__ void put(T* base, uint32_t idx, T v)
+{
+    PP_GLOBAL char* const g = reinterpret_cast<PP_GLOBAL char*>(gptr(base));
+    uint32_t off = idx * (uint32_t)sizeof(T);
+    // opaque here, so that the widening of the offset stays next to the store
+    // and the store can take the scalar base with a 32-bit lane offset
+    asm volatile("" : "+v"(off));
+    *reinterpret_cast<PP_GLOBAL T*>(g + off) = v;
+}
+
 // Everything one tile needs about its buffer, dialect and outputs.
 struct TileArgs {
     const uint8_t* in;
@@ -429,9 +443,6 @@ struct TileSmem {
     uint16_t recend[RCAP];  // local field index of each record delimiter
     uint32_t ctl[TILE / 32];  // control-symbol bitmap of the tile
     ColDesc cols[PP_MAX_COLUMNS];
-    // column outputs offset to this tile's first record, as separate arrays of
-    // 8-byte entries (cheap 32-bit LDS indexing)
-    u64 cbv[PP_MAX_COLUMNS], cbm[PP_MAX_COLUMNS], cbe[PP_MAX_COLUMNS];
     double pow10[24];  // 10^k, k <= 22, for the decimal conversions
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
@@ -476,9 +487,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     uint16_t* const s_recend = sm.recend;
     uint32_t* const s_ctl = sm.ctl;
     ColDesc* const s_cols = sm.cols;
-    u64* const s_cbv = sm.cbv;
-    u64* const s_cbm = sm.cbm;
-    u64* const s_cbe = sm.cbe;
     SV<NS8>* const s_wsv = reinterpret_cast<SV<NS8>*>(&sm.wsv[0][0]);
     Cnt* const s_wcnt = sm.wcnt;
     uint32_t& s_anyctl = sm.anyctl;
@@ -843,10 +851,11 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
 
-    const int64_t R0 = (int64_t)s_pref[0];
-    const int64_t F0 = (int64_t)s_pref[1];
-    const int64_t C0 = (int64_t)(s_pref[2] & kColVal);  // always absolute: seeded with (abs, 0)
-    const u64 lastw = s_pref[3];
+    // the tile's prefixes as scalars (every lane is active here)
+    const int64_t R0 = (int64_t)readlane0_64(s_pref[0]);
+    const int64_t F0 = (int64_t)readlane0_64(s_pref[1]);
+    const int64_t C0 = (int64_t)(readlane0_64(s_pref[2]) & kColVal);  // always absolute: seeded with (abs, 0)
+    const u64 lastw = readlane0_64(s_pref[3]);
     const int ncols = p.ncols;
     const ByteSrc src{s_bytes, p.in, tile_start, TILE};
     const bool last_has = (lastw & kLastHas) != 0;
@@ -877,13 +886,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 
     int64_t nerr = 0, nragged = 0;
     if (staged) {
-        if (tid < ncols) {  // column outputs as seen from this tile's first record
-            const ColDesc d = s_cols[tid];
-            s_cbv[tid] = (u64)((char*)d.values + R0 * 8);
-            s_cbm[tid] = (u64)(d.valid + R0);
-            s_cbe[tid] = (u64)(d.str_end + R0);
-        }
-        __syncthreads();
         {
             const int64_t roomf = p.cap_fields - F0;
             const int kf = roomf < Ft ? (int)(roomf < 0 ? 0 : roomf) : Ft;
@@ -891,13 +893,13 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             int32_t* const ci = p.column_ids + F0;
             const int open_end = Rt ? (int)s_recend[0] + 1 : Ft;  // fields of the record open at the tile start
             for (int k = tid; k < kf; k += NT) {
-                gptr(fo)[k] = tile_start + 1 + s_pos[k];
-                gptr(ci)[k] = (int32_t)s_colid[k] + (k < open_end ? (int32_t)C0 : 0);
+                put(fo, (uint32_t)k, tile_start + 1 + s_pos[k]);
+                put(ci, (uint32_t)k, (int32_t)s_colid[k] + (k < open_end ? (int32_t)C0 : 0));
             }
             const int64_t roomr = p.cap_records - R0;
             const int kr = roomr < Rt ? (int)(roomr < 0 ? 0 : roomr) : Rt;
             int64_t* const ro = p.record_offsets + R0 + 1;
-            for (int k = tid; k < kr; k += NT) gptr(ro)[k] = F0 + 1 + s_recend[k];
+            for (int k = tid; k < kr; k += NT) put(ro, (uint32_t)k, F0 + 1 + s_recend[k]);
         }
 
         // ---- 7. typed columns ---------------------------------------------------------------
@@ -921,6 +923,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         const uint32_t per = ncols ? ((uint32_t)ncols + groups - 1u) / groups : 0u;  // columns per group
         groups = per ? ((uint32_t)ncols + per - 1u) / per : 0u;
         const uint32_t witems = nrb * groups;
+        using KCol = const __attribute__((address_space(4))) ColDesc;
+        KCol* const kcols = (KCol*)p.cols;
         // the wavefront's index as a scalar (every lane is active here)
         const uint32_t wv = __builtin_amdgcn_readfirstlane((uint32_t)wave);
         for (uint32_t wi = wv; wi < witems; wi += (uint32_t)NW) {
@@ -938,19 +942,21 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const bool st = lr < lr_cap;
             int pend = -1;  // position of the delimiter before the next field, once known
             for (uint32_t c = cb; c < ce; ++c) {
-                // Column c's type and bases, read while lane 0 of the block
-                // (record rb*64 < nrec) is active, as scalars.
-                const uint32_t ty = __builtin_amdgcn_readfirstlane((uint32_t)s_cols[c].type);
-                u64* const vals = (u64*)readlane0_64(s_cbv[c]);
-                uint8_t* const valid = (uint8_t*)readlane0_64(s_cbm[c]);
-                int64_t* const ends = (int64_t*)readlane0_64(s_cbe[c]);
+                // Column c's type and output bases through the scalar cache (c
+                // is wavefront-uniform; the descriptors stay fixed during the
+                // launch), offset to the tile's first record.
+                const KCol& kc = kcols[c];
+                const uint32_t ty = (uint32_t)kc.type;
+                u64* const vals = (u64*)kc.values + R0;
+                uint8_t* const valid = (uint8_t*)kc.valid + R0;
+                int64_t* const ends = (int64_t*)kc.str_end + R0;
                 if (c < cf) continue;
                 const uint32_t L = first + c - cf;
                 if (__builtin_expect(L >= end1, 0)) {
                     if (lr < (uint32_t)Rt && st && ty != PP_SKIP) {  // missing column of a short record
-                        gptr(vals)[lr] = 0;
-                        gptr(valid)[lr] = 0;
-                        if (ty == PP_STRING) gptr(ends)[lr] = 0;
+                        put(vals, lr, (u64)0);
+                        put(valid, lr, (uint8_t)0);
+                        if (ty == PP_STRING) put(ends, lr, (int64_t)0);
                     }
                     continue;
                 }
@@ -975,14 +981,14 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 }
                 if (ty == PP_STRING) {
                     if (st) {
-                        gptr((int64_t*)vals)[lr] = tile_start + bb;
-                        gptr(ends)[lr] = tile_start + ee;
-                        gptr(valid)[lr] = 1;
+                        put((int64_t*)vals, lr, tile_start + bb);
+                        put(ends, lr, tile_start + ee);
+                        put(valid, lr, (uint8_t)1);
                     }
                 } else if (ee == bb) {  // empty: the column default, not an error
                     if (st) {
-                        gptr(vals)[lr] = 0;
-                        gptr(valid)[lr] = 0;
+                        put(vals, lr, (u64)0);
+                        put(valid, lr, (uint8_t)0);
                     }
                 } else {
                     const int len = ee - bb;
@@ -1005,8 +1011,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     if (__builtin_expect(r < 0, 0)) r = convert_general((int)ty, src, tile_start + bb, tile_start + ee, &bits);
                     nerr += r == 0;
                     if (st) {
-                        gptr(vals)[lr] = r ? bits : 0ull;
-                        gptr(valid)[lr] = (uint8_t)r;
+                        put(vals, lr, r ? bits : 0ull);
+                        put(valid, lr, (uint8_t)r);
                     }
                 }
             }
