@@ -437,6 +437,7 @@ struct TileSmem {
     static constexpr int RCAP = TILE / 16;  // records staged per tile
     uint32_t tnext[512];  // byte -> next state of every state
     uint32_t tcomb[512];  // byte -> per state (next*8 | tag<<6)
+    uint8_t after_delim[256];  // byte -> the state after it as a delimiter (0xff: depends on the state)
     __attribute__((aligned(16))) uint8_t bytes[TILE + 32];  // +32: register windows read past the end
     uint16_t pos[FCAP];     // tile-relative delimiter positions
     uint16_t colid[FCAP];   // column of the field each delimiter closes
@@ -462,6 +463,25 @@ __device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& s
     for (int k = tid; k < (NS8 ? 512 : 256); k += NT) {
         sm.tnext[k] = gptr(p.tables)[k];
         sm.tcomb[k] = gptr(p.tables)[512 + k];
+    }
+    // For each byte, the state the DFA enters when the byte closes a field or
+    // record, if the same from every state in which it does (typical: the
+    // start of the next field); else 0xff. States without a delimiter
+    // transition on the byte carry no tag and drop out.
+    for (int b = tid; b < 256; b += NT) {
+        const uint32_t lo = gptr(p.tables)[512 + (NS8 ? 2 * b : b)];
+        const uint32_t hi = NS8 ? gptr(p.tables)[512 + 2 * b + 1] : 0u;
+        uint32_t a = 0xffu, any = 0u, same = 1u;
+        for (int st = 0; st < (NS8 ? 8 : 4); ++st) {
+            const uint32_t x = ((st < 4 ? lo : hi) >> (8 * (st & 3))) & 0xffu;
+            if (x & 0x80u) {  // tag bit 1: a field or record delimiter
+                const uint32_t nx = (x >> 3) & 7u;
+                same &= !any || nx == a;
+                a = nx;
+                any = 1u;
+            }
+        }
+        sm.after_delim[b] = (uint8_t)(any && same ? a : 0xffu);
     }
     for (int c = tid; c < p.ncols; c += NT) sm.cols[c] = p.cols[c];
 }
@@ -541,10 +561,10 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         }
     }
     auto byte_at = [&](int i) -> uint32_t { return (wd[i >> 2] >> ((i & 3) * 8)) & 0xffu; };
-    // Cold paths (a chunk shorter than B, a second tag pass, the searches
-    // below) walk the chunk in rolled loops over its LDS copy: the unrolled
-    // forms would add kilobytes of code that every tile's hot path shares
-    // the instruction cache with.
+    // Cold paths (a chunk shorter than B, the state searches below) walk the
+    // chunk in rolled loops over its LDS copy: the unrolled forms would add
+    // kilobytes of code that every tile's hot path shares the instruction
+    // cache with.
     const uint8_t* const cb_lds = s_bytes + c0;
 
     // ---- 2. multi-state pass ----------------------------------------------------------
@@ -660,7 +680,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
     const uint32_t s_start = sv_get(ex, s_s0);
-    if (__builtin_expect(s_start != s_guess, 0)) tag_pass(s_start, false);  // rare: the rolled form
+    if (s_start != s_guess) tag_pass(s_start, true);  // typically the tile's first chunk
     const uint32_t s_end = (s8 & 0x38u) >> 3;
     const M dmask = p1, rmask = p1 & p0, cmask = p0 & ~p1;
     const int64_t cstart = tile_start + c0;
@@ -732,9 +752,12 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         uint32_t sa = 0;
         if (!vend) {
             const int hb = msb(dmask);
-            uint32_t r8 = s_start * 8u;
-            for (int i = 0; i <= hb; ++i) r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
-            sa = r8 >> 3;
+            sa = sm.after_delim[cb_lds[hb]];
+            if (sa == 0xffu) {  // the DFA's state after this delimiter byte varies: walk the chunk
+                uint32_t r8 = s_start * 8u;
+                for (int i = 0; i <= hb; ++i) r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
+                sa = r8 >> 3;
+            }
         }
         s_last_sa = sa;
     }
