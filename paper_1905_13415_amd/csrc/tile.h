@@ -218,6 +218,22 @@ __device__ inline SV<NS8> shfl_down_sv(SV<NS8> v, int d)
     return r;
 }
 
+// The even bits of x into the low half and the odd bits into the high half,
+// each in order (four swap steps of the standard bit de-interleave).
+__device__ __forceinline__ uint32_t unzip_bits(uint32_t x)
+{
+    uint32_t t;
+    t = (x ^ (x >> 1)) & 0x22222222u;
+    x ^= t ^ (t << 1);
+    t = (x ^ (x >> 2)) & 0x0C0C0C0Cu;
+    x ^= t ^ (t << 2);
+    t = (x ^ (x >> 4)) & 0x00F000F0u;
+    x ^= t ^ (t << 4);
+    t = (x ^ (x >> 8)) & 0x0000FF00u;
+    x ^= t ^ (t << 8);
+    return x;
+}
+
 // ---- wavefront scans through DPP -------------------------------------------------
 // A DPP move reads another lane's register within the same instruction (no LDS
 // round trip). Controls (GFX9 encoding): row_shr:n = 0x110 + n within rows of
@@ -593,16 +609,19 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const SV<NS8> incl = wave_scan_sv<NS8>(vec);
     if (lane == 63) s_wsv[wave] = incl;
     __syncthreads();
-    SV<NS8> wpre = sv_identity<NS8>();
-    for (int w = 0; w < wave; ++w) wpre = compose(wpre, s_wsv[w]);
+    // the wavefront aggregates in one unrolled pass (their reads go out
+    // together): the prefix of the wavefronts before this one, and the tile's
+    SV<NS8> wpre = sv_identity<NS8>(), agg = sv_identity<NS8>();
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const SV<NS8> v = s_wsv[w];
+        if (w < wave) wpre = compose(wpre, v);
+        agg = compose(agg, v);
+    }
     const SV<NS8> ex = compose(wpre, wave_prev_sv<NS8>(incl));  // exclusive prefix of this chunk within the tile
 
     // the tile's aggregate goes out first; successors wait on it
-    SV<NS8> agg = sv_identity<NS8>();
-    if (wave == 0) {
-        for (int w = 0; w < NW; ++w) agg = compose(agg, s_wsv[w]);
-        if (lane == 0) publish(tw + W_STATE, (tile == 0 ? kIncl : kAgg) | sv_to_nib(agg));
-    }
+    if (wave == 0 && lane == 0) publish(tw + W_STATE, (tile == 0 ? kIncl : kAgg) | sv_to_nib(agg));
 
     // ---- 4. tag pass ----------------------------------------------------------------------
     // x = tcomb[b] >> (8*state): bits 3-5 next state * 8, bit 6 tag bit 0, bit 7 tag bit 1.
@@ -630,8 +649,31 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             p1 |= (M)(x >> 7) << i;
         };
         if (hot && len == B) {
+            // Unrolled: the two tag bits of byte i go to bits 2(i%16) and
+            // 2(i%16)+1 of word i/16 (one shift-or per byte), separated into
+            // the two bitmaps once at the end.
+            uint32_t il[B / 16];
 #pragma unroll
-            for (int i = 0; i < B; ++i) tstep(i, byte_at(i));
+            for (int k = 0; k < B / 16; ++k) il[k] = 0u;
+#pragma unroll
+            for (int i = 0; i < B; ++i) {
+                const uint32_t b = byte_at(i);
+                uint32_t x;
+                if constexpr (NS8) {
+                    const uint32_t e = s_tcomb[2 * b + (s8 >> 5)];
+                    x = __builtin_amdgcn_ubfe(e, s8 & 31u, 8);
+                } else {
+                    x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
+                }
+                s8 = NS8 ? (x & 0x38u) : x;
+                il[i >> 4] |= (x >> 6) << (2 * (i & 15));
+            }
+#pragma unroll
+            for (int k = 0; k < B / 16; ++k) {
+                const uint32_t w = unzip_bits(il[k]);
+                p0 |= (M)(w & 0xffffu) << (16 * k);
+                p1 |= (M)(w >> 16) << (16 * k);
+            }
         } else {
             for (int i = 0; i < len; ++i) tstep(i, cb_lds[i]);
         }
@@ -740,11 +782,14 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const Cnt cin = wave_scan_cnt(mine);
     if (lane == 63) s_wcnt[wave] = cin;
     __syncthreads();
-    Cnt cpre = {0u, 0u, 0u, 0u};
-    for (int w = 0; w < wave; ++w) cpre = cnt_combine(cpre, s_wcnt[w]);
+    Cnt cpre = {0u, 0u, 0u, 0u}, tagg = {0u, 0u, 0u, 0u};  // wavefronts before this one; the whole tile
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const Cnt v = s_wcnt[w];
+        if (w < wave) cpre = cnt_combine(cpre, v);
+        tagg = cnt_combine(tagg, v);
+    }
     const Cnt cex = cnt_combine(cpre, dpp_cnt<0x138, 0xF>(cin));  // previous lane's (zero in lane 0)
-    Cnt tagg = {0u, 0u, 0u, 0u};
-    for (int w = 0; w < NW; ++w) tagg = cnt_combine(tagg, s_wcnt[w]);
 
     // state after the tile's last delimiter, from the chunk that holds it (the
     // one whose own last delimiter is the tile's: positions are unique)
