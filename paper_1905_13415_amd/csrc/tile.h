@@ -364,15 +364,18 @@ __device__ inline Tot tot_from_agg(u64 a0, u64 a1, int64_t tile_start)
 
 // Reads input bytes for conversion: from the LDS tile when inside it, from
 // HBM for the head of a field that began in an earlier tile.
+// Bytes kept in LDS before a tile (not for the first tile of a buffer, whose
+// fields never start earlier).
+constexpr int kLdsBefore = 64;
+
 struct ByteSrc {
-    const uint8_t* lds;
+    const uint8_t* lds;  // the tile; lds[-kLdsBefore, 0) hold the bytes before it
     const uint8_t* g;
     int64_t tile_start;
-    int tile_size;  // bytes of the LDS tile buffer (a multiple of 4)
     __device__ uint32_t operator()(int64_t pos) const
     {
         int64_t r = pos - tile_start;
-        return r >= 0 ? lds[r] : gptr(g)[pos];
+        return r >= -kLdsBefore ? lds[r] : gptr(g)[pos];
     }
 };
 
@@ -454,7 +457,10 @@ struct TileSmem {
     uint32_t tnext[512];  // byte -> next state of every state
     uint32_t tcomb[512];  // byte -> per state (next*8 | tag<<6)
     uint8_t after_delim[256];  // byte -> the state after it as a delimiter (0xff: depends on the state)
-    __attribute__((aligned(16))) uint8_t bytes[TILE + 32];  // +32: register windows read past the end
+    // the tile at offset PRE, preceded by the PRE bytes before it (where the
+    // tile's first field usually begins); +32: register windows read past the end
+    static constexpr int PRE = kLdsBefore;
+    __attribute__((aligned(16))) uint8_t bytes[PRE + TILE + 32];
     uint16_t pos[FCAP];     // tile-relative delimiter positions
     uint16_t colid[FCAP];   // column of the field each delimiter closes
     uint16_t recend[RCAP];  // local field index of each record delimiter
@@ -517,7 +523,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     static_assert(TILE <= 32768, "u16 positions");
     uint32_t* const s_tnext = sm.tnext;
     uint32_t* const s_tcomb = sm.tcomb;
-    uint8_t* const s_bytes = sm.bytes;
+    uint8_t* const s_bytes = sm.bytes + TileSmem<NT, B>::PRE;  // the tile; s_bytes[-PRE, 0) precede it
     uint16_t* const s_pos = sm.pos;
     uint16_t* const s_colid = sm.colid;
     uint16_t* const s_recend = sm.recend;
@@ -561,6 +567,17 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             for (int k = tid; k < TILE / 16; k += NT) d4[k] = __builtin_nontemporal_load(gptr(s4) + k);
         } else {
             for (int k = tid; k < TILE; k += NT) s_bytes[k] = k < tile_len ? gptr(src)[k] : 0;
+        }
+        constexpr int PRE = TileSmem<NT, B>::PRE;
+        if (tile_start >= PRE) {  // the bytes just before the tile
+            const uint8_t* pre = src - PRE;
+            if ((((uintptr_t)pre) & 15) == 0) {
+                if (tid < PRE / 16)
+                    reinterpret_cast<u32x4*>(s_bytes - PRE)[tid] =
+                        __builtin_nontemporal_load(gptr(reinterpret_cast<const u32x4*>(pre)) + tid);
+            } else if (tid < PRE) {
+                s_bytes[tid - PRE] = gptr(pre)[tid];
+            }
         }
     }
     __syncthreads();
@@ -925,7 +942,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const int64_t C0 = (int64_t)(readlane0_64(s_pref[2]) & kColVal);  // always absolute: seeded with (abs, 0)
     const u64 lastw = readlane0_64(s_pref[3]);
     const int ncols = p.ncols;
-    const ByteSrc src{s_bytes, p.in, tile_start, TILE};
+    const ByteSrc src{s_bytes, p.in, tile_start};
     const bool last_has = (lastw & kLastHas) != 0;
     const int64_t last_pos = (int64_t)(lastw & kLastPos);
     const uint32_t last_sa = (uint32_t)((lastw >> 56) & 0xf);
@@ -937,7 +954,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const int r = (int)(b - tile_start);
             return (s_ctl[r >> 5] >> (r & 31)) & 1u;
         }
-        const uint32_t by = gptr(p.in)[b];
+        const uint32_t by = b >= tile_start - kLdsBefore ? s_bytes[b - tile_start] : gptr(p.in)[b];
         const uint32_t s8 = last_sa * 8u;
         uint32_t x;
         if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (s8 >> 5)], s8 & 31u, 8);
