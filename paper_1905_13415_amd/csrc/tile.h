@@ -1045,24 +1045,34 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     }
                     continue;
                 }
-                if (__builtin_expect(L == 0, 0)) {  // may begin in an earlier tile: general path
+                int bb, ee;  // tile-relative span; the first field's may begin before the tile
+                if (__builtin_expect(L == 0, 0)) {
                     const int64_t e = tile_start + s_pos[0];
                     pend = s_pos[0];
-                    if (ty != PP_SKIP) {
-                        const int64_t bb = last_has ? last_pos + 1 : 0;
-                        const bool cfst = e > bb && ctl_at_begin(bb);
-                        const bool clst = e > bb && ctl_at_end(e);
-                        nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, bb, e, cfst, clst);
+                    if (ty == PP_SKIP) continue;
+                    const int64_t hb = last_has ? last_pos + 1 : 0;
+                    if (hb < tile_start - kLdsBefore) {  // begins further back than LDS holds: general path
+                        const bool cfst = e > hb && ctl_at_begin(hb);
+                        const bool clst = e > hb && ctl_at_end(e);
+                        nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, hb, e, cfst, clst);
+                        continue;
                     }
-                    continue;
-                }
-                int bb = (pend >= 0 ? pend : (int)s_pos[L - 1]) + 1;
-                int ee = s_pos[L];
-                pend = ee;
-                if (ty == PP_SKIP) continue;
-                if (anyctl && ee > bb) {  // strip enclosing control symbols
-                    if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
-                    if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
+                    bb = (int)(hb - tile_start);
+                    ee = s_pos[0];
+                    if (ee > bb) {  // strip enclosing control symbols
+                        const bool cfst = ctl_at_begin(hb), clst = ctl_at_end(e);
+                        if (cfst) ++bb;
+                        if (ee - 1 >= bb && clst) --ee;
+                    }
+                } else {
+                    bb = (pend >= 0 ? pend : (int)s_pos[L - 1]) + 1;
+                    ee = s_pos[L];
+                    pend = ee;
+                    if (ty == PP_SKIP) continue;
+                    if (anyctl && ee > bb) {  // strip enclosing control symbols
+                        if ((s_ctl[bb >> 5] >> (bb & 31)) & 1u) ++bb;
+                        if (ee - 1 >= bb && ((s_ctl[(ee - 1) >> 5] >> ((ee - 1) & 31)) & 1u)) --ee;
+                    }
                 }
                 if (ty == PP_STRING) {
                     if (st) {
