@@ -72,7 +72,8 @@ __device__ __forceinline__ const PP_GLOBAL T* gptr(const T* ptr)
 
 // Element `idx` of an output array at a 32-bit byte offset from a
 // wavefront-uniform base: the store takes the base in scalar registers and
-// only the offset per lane.
+// only the offset per lane. Outputs are never read back by the kernel, so
+// the store is a streaming (nontemporal) one.
 template <class T>
 __device__ __forceinline__ void put(T* base, uint32_t idx, T v)
 {
@@ -81,7 +82,7 @@ __device__ __forceinline__ void put(T* base, uint32_t idx, T v)
     // opaque here, so that the widening of the offset stays next to the store
     // and the store can take the scalar base with a 32-bit lane offset
     asm volatile("" : "+v"(off));
-    *reinterpret_cast<PP_GLOBAL T*>(g + off) = v;
+    __builtin_nontemporal_store(v, reinterpret_cast<PP_GLOBAL T*>(g + off));
 }
 
 // Everything one tile needs about its buffer, dialect and outputs.
