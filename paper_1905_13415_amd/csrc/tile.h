@@ -458,6 +458,7 @@ struct TileSmem {
     uint32_t tnext[512];  // byte -> next state of every state
     uint32_t tcomb[512];  // byte -> per state (next*8 | tag<<6)
     uint8_t after_delim[256];  // byte -> the state after it as a delimiter (0xff: depends on the state)
+    uint8_t ctl_any[256];      // byte -> 1 if it is a control symbol (a quote) in some state
     // the tile at offset PRE, preceded by the PRE bytes before it (where the
     // tile's first field usually begins); +32: register windows read past the end
     static constexpr int PRE = kLdsBefore;
@@ -470,7 +471,7 @@ struct TileSmem {
     double pow10[24];  // 10^k, k <= 22, for the decimal conversions
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
-    uint32_t anyctl, s0, fin, last_sa, ctl_last;
+    uint32_t anyctl, s0, fin, last_sa, ctl_last, guess;
     u64 pref[4];
     u64 err, ragged;
 };
@@ -494,9 +495,10 @@ __device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& s
     for (int b = tid; b < 256; b += NT) {
         const uint32_t lo = gptr(p.tables)[512 + (NS8 ? 2 * b : b)];
         const uint32_t hi = NS8 ? gptr(p.tables)[512 + 2 * b + 1] : 0u;
-        uint32_t a = 0xffu, any = 0u, same = 1u;
+        uint32_t a = 0xffu, any = 0u, same = 1u, ctl = 0u;
         for (int st = 0; st < (NS8 ? 8 : 4); ++st) {
             const uint32_t x = ((st < 4 ? lo : hi) >> (8 * (st & 3))) & 0xffu;
+            ctl |= (x >> 6) == kTagControl;
             if (x & 0x80u) {  // tag bit 1: a field or record delimiter
                 const uint32_t nx = (x >> 3) & 7u;
                 same &= !any || nx == a;
@@ -505,6 +507,7 @@ __device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& s
             }
         }
         sm.after_delim[b] = (uint8_t)(any && same ? a : 0xffu);
+        sm.ctl_any[b] = (uint8_t)ctl;
     }
     for (int c = tid; c < p.ncols; c += NT) sm.cols[c] = p.cols[c];
 }
@@ -626,6 +629,30 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     // ---- 3. composition scan ------------------------------------------------------------
     const SV<NS8> incl = wave_scan_sv<NS8>(vec);
     if (lane == 63) s_wsv[wave] = incl;
+    // A guess of the tile's start state for the speculative tag pass: the
+    // DFA run from its start state over the 64 bytes before the tile (one
+    // byte per lane, composed by a wavefront scan), when those bytes hold no
+    // control symbol. It tracks the field structure up to the tile start
+    // (typically the middle of a field), so the tile's first chunk is
+    // usually spared its second tag pass; the lookback still decides.
+    // Otherwise the guess is the DFA's start state.
+    if (wave == 0) {
+        uint32_t tile_guess = (uint32_t)p.start_state;
+        if (tile_start >= kLdsBefore) {
+            const uint32_t b = s_bytes[lane - kLdsBefore];
+            SV<NS8> t;
+            if constexpr (NS8) { t.lo = s_tnext[2 * b]; t.hi = s_tnext[2 * b + 1]; }
+            else { t.lo = s_tnext[b]; t.hi = 0; }
+            const SV<NS8> all = wave_scan_sv<NS8>(t);
+            SV<NS8> v;
+            v.lo = (uint32_t)__builtin_amdgcn_readlane((int)all.lo, 63);
+            v.hi = NS8 ? (uint32_t)__builtin_amdgcn_readlane((int)all.hi, 63) : 0u;
+            // trusted only when no byte there can be a control symbol (a quote
+            // could flip the quoting of everything after it)
+            if (ballot(sm.ctl_any[b] != 0) == 0) tile_guess = sv_get(v, (uint32_t)p.start_state);
+        }
+        if (lane == 0) sm.guess = tile_guess;
+    }
     __syncthreads();
     // the wavefront aggregates in one unrolled pass (their reads go out
     // together): the prefix of the wavefronts before this one, and the tile's
@@ -643,8 +670,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 
     // ---- 4. tag pass ----------------------------------------------------------------------
     // x = tcomb[b] >> (8*state): bits 3-5 next state * 8, bit 6 tag bit 0, bit 7 tag bit 1.
-    // It runs first under a guess, the tile starting in the DFA's start state,
-    // while the state lookback is still to come; chunks whose start state the
+    // It runs first under a guess of the tile's start state (above), while
+    // the state lookback is still to come; chunks whose start state the
     // lookback then changes run it again.
     M p0 = 0, p1 = 0;
     uint32_t s8 = 0;
@@ -696,7 +723,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             for (int i = 0; i < len; ++i) tstep(i, cb_lds[i]);
         }
     };
-    const uint32_t s_guess = sv_get(ex, (uint32_t)p.start_state);
+    const uint32_t s_guess = sv_get(ex, sm.guess);
     tag_pass(s_guess, true);
 
     if (wave == 0) {
