@@ -4,32 +4,37 @@
 // One workgroup of NT threads owns a tile of NT*B input bytes; each thread
 // owns a chunk of B bytes (the per-thread chunks of Sec. 3.1). Per tile, in
 // one kernel:
-//   1. stage the tile in LDS with 16-byte loads; every thread keeps its
-//      chunk in registers;
+//   1. stage the tile in LDS with 16-byte loads, after the 64 bytes that
+//      precede it (where the tile's first field usually begins); every
+//      thread keeps its chunk in registers;
 //   2. multi-state pass (Sec. 3.1): per chunk, one DFA instance per state,
 //      packed one byte per state in a register; a step is one v_perm_b32
 //      (<= 4 states) or two (<= 8 states) that looks every instance up in
 //      the byte's transition row: the chunk's state-transition vector;
-//   3. exclusive composition scan ((a o b)_i = b[a_i], Sec. 3.1): wave scan
-//      by shuffles, block scan through LDS, device scan by decoupled lookback
-//      (the single-pass scan the paper builds on, Sec. 2) in which one
-//      wavefront polls 64 predecessor tiles at a time;
+//   3. exclusive composition scan ((a o b)_i = b[a_i], Sec. 3.1): wavefront
+//      scan through DPP moves, block scan through LDS, device scan by
+//      decoupled lookback (the single-pass scan the paper builds on, Sec. 2)
+//      in which one wavefront polls 64 predecessor tiles at a time;
 //   4. tag pass from the chunk's start state into register bitmaps of record
-//      delimiters, field delimiters and control symbols (Sec. 3.1);
+//      delimiters, field delimiters and control symbols (Sec. 3.1); it runs
+//      under a guessed start state while the lookback is pending, and again
+//      for chunks the guess got wrong;
 //   5. record counts (+), field counts (+), column carries (the abs/rel
 //      operator of Sec. 3.2) and the last delimiter position, scanned the
 //      same way;
 //   6. delimiter positions, column ids and record ends staged in LDS, then
 //      written coalesced as field offsets, column ids and record offsets;
-//   7. typed conversion (Sec. 3.3): a thread walks one record's fields of a
-//      contiguous group of columns; lanes of a wavefront hold consecutive
-//      records, so at each step they convert the same column (one type) and
-//      their stores into that typed column are contiguous. This takes the
-//      place of the paper's radix-sort partition by column tag: the (record,
-//      column) pair addresses the output slot directly.
+//   7. typed conversion (Sec. 3.3): a wavefront takes a block of 64 records
+//      and a contiguous group of columns, a lane one record, and walks the
+//      group's fields in order; every lane is at the same column, so the
+//      type is wavefront-uniform and the stores into the typed column are
+//      contiguous. This takes the place of the paper's radix-sort partition
+//      by column tag: the (record, column) pair addresses the output slot
+//      directly.
 // Tiles with more fields or records than the LDS staging holds take a
 // per-thread path for steps 6-7 that gives the same outputs.
-// The input is read from HBM once; per-symbol metadata never leaves the chip.
+// The input is read from HBM once; per-symbol metadata never leaves the chip;
+// outputs are written with streaming stores.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
