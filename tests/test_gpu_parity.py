@@ -5,7 +5,8 @@ shapes) with ragged tails; the edge cases cover empty input, inputs ending
 at and off tile boundaries, fields and quotes spanning tiles, tiles of
 nothing but delimiters or tiny records (the per-thread fallback path),
 invalid input, unterminated quotes, capacity, an unaligned input pointer,
-3- to 8-state DFAs, and hard float conversions.
+3- to 8-state DFAs, hard float conversions, and a tile's first field of each
+type beginning 0-71, 100 and 200 bytes before the tile.
 """
 import random
 
@@ -274,3 +275,29 @@ def test_timestamps_all_years():
         rows.append(f"{y:04d}-{mo:02d}-{d:02d}{sep}{h:02d}:{mi:02d}:{s:02d},{y:04d}-{mo:02d}-{d:02d}")
     data = ("\n".join(rows) + "\n").encode()
     assert_same(u8(data), D.csv4(), [D.TIMESTAMP_S, D.DATE_DAYS])
+
+
+# ---- the tile's first field, by how far before the tile it begins -------------------
+
+HEAD_SCHEMA = [D.STRING, D.INT64, D.FLOAT64, D.TIMESTAMP_S, D.STRING]
+HEAD_FIELDS = ["-1234567", "-12345.6789", "2019-03-04 05:06:07", '"q,u""o"']
+
+
+@pytest.mark.parametrize("k", range(1, 5), ids=["int", "float", "timestamp", "quoted"])
+def test_first_field_of_tile_at_every_offset(k):
+    # Field k of the second record begins d bytes before the second tile: from
+    # the tile boundary itself, through the 64 bytes the kernel keeps before a
+    # tile, to beyond them (the general path). The bytes before the tile hold
+    # no quote for k < 4 (the start-state guess from them is taken) and a
+    # quote for k = 4 (it is not).
+    tail = "".join(f"{i},{i * 7},{i}.25,2020-01-0{1 + i % 9} 00:00:0{i % 10},s{i}\n" for i in range(40))
+    for d in list(range(0, 72)) + [100, 200]:
+        rec = ["x", "7", "1.5", "2001-02-03 04:05:06", "y"]
+        rec[k] = HEAD_FIELDS[k - 1]
+        between = sum(len(f) + 1 for f in rec[1:k])  # fields 1..k-1 and their commas
+        first = "p" * 10 + ",1,2.5,1999-12-31 23:59:59,z\n"
+        pad = TILE - d - len(first) - 1 - between
+        rec[0] = "w" * pad
+        data = (first + ",".join(rec) + "\n" + tail * 3).encode()
+        assert data.find(HEAD_FIELDS[k - 1].encode(), len(first)) == TILE - d
+        assert_same(u8(data), D.csv4(), HEAD_SCHEMA)
