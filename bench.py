@@ -245,8 +245,11 @@ def bench_c1(args):
     dev = torch.device("cuda:0")
     d_in = torch.from_numpy(g.data).to(dev)
     out = pp.alloc_outputs(types, R, F, device=dev)
-    ws = torch.empty(pp.workspace_size(n), dtype=torch.uint8, device=dev)
-    call = pp.Call(d_in, n, dfa, types, out, ws)
+    # launch shape from the autotuner: the input is a few dozen default
+    # tiles, so smaller tiles can spread it over more of the chip
+    best, tune = pp.autotune_parse(d_in, dfa, types, out, reps=10)
+    ws = torch.empty(pp.workspace_size(n, best), dtype=torch.uint8, device=dev)
+    call = pp.Call(d_in, n, dfa, types, out, ws, opts=best)
     stream = torch.cuda.current_stream()
     steps = max(args.steps, 50)
     for _ in range(max(args.warmup, 5)):
@@ -283,7 +286,10 @@ def bench_c1(args):
         "data": "synthetic (seeded RFC-4180-style CSV; no dataset used)",
         "config": {"workload": "c1: 10,000 records x 8 columns (2 int64, 2 float64, 1 timestamp, 3 strings, "
                                "20% quoted with embedded commas, LF and doubled quotes), csv4 DFA, one plain launch",
-                   "bytes": n, "records": R, "fields": F},
+                   "bytes": n, "records": R, "fields": F,
+                   "block_threads": best.block_threads, "bytes_per_thread": best.bytes_per_thread},
+        "autotune_us_per_shape": {f"{o.block_threads}x{o.bytes_per_thread}": round(m * 1e3, 2)
+                                  for o, m in zip(pp.shapes(), tune["ms"]) if m >= 0},
         "latency_us": {"p50": round(med, 2), "p10": round(per[len(per) // 10], 2),
                        "p90": round(per[(9 * len(per)) // 10], 2), "min": round(per[0], 2)},
         "in_out_gbs": round((n + outb) / (med / 1e6) / 1e9, 2),
