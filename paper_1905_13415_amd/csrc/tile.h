@@ -476,7 +476,7 @@ struct TileSmem {
     double pow10[24];  // 10^k, k <= 22, for the decimal conversions
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
-    uint32_t anyctl, s0, fin, last_sa, ctl_last, guess;
+    uint32_t anyctl, s0, fin, last_sa, guess;
     u64 pref[4];
     u64 err, ragged;
 };
@@ -544,7 +544,6 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     uint32_t& s_s0 = sm.s0;
     uint32_t& s_final = sm.fin;
     uint32_t& s_last_sa = sm.last_sa;
-    uint32_t& s_ctl_last = sm.ctl_last;
     u64* const s_pref = sm.pref;
     u64& s_err = sm.err;
     u64& s_ragged = sm.ragged;
@@ -841,23 +840,29 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     const Cnt cex = cnt_combine(cpre, dpp_cnt<0x138, 0xF>(cin));  // previous lane's (zero in lane 0)
 
-    // state after the tile's last delimiter, from the chunk that holds it (the
-    // one whose own last delimiter is the tile's: positions are unique)
-    if (mine.nf && mine.last == tagg.last) {
-        uint32_t sa = 0;
-        if (!vend) {
+    // The tile's aggregate needs the DFA state after its last delimiter and
+    // the control bit of its last byte. Every thread reads both from LDS (the
+    // delimiter byte's entry in the after-delimiter table; the control
+    // bitmap, complete since the barrier above), so no further barrier is
+    // needed, except where the state after that byte depends on the state
+    // before it: then the chunk holding the delimiter (the one whose own last
+    // delimiter is the tile's: positions are unique) walks to it.
+    const uint32_t lastrel = tagg.last;                      // position + 1, 0 = none
+    const bool virt_end = lastrel == (uint32_t)tile_len + 1u;  // the end of input closes the last record
+    uint32_t my_last_sa = 0;
+    if (lastrel && !virt_end) my_last_sa = sm.after_delim[s_bytes[lastrel - 1u]];
+    if (my_last_sa == 0xffu) {  // the same for every thread: one byte of LDS decides
+        if (mine.nf && mine.last == tagg.last) {
             const int hb = msb(dmask);
-            sa = sm.after_delim[cb_lds[hb]];
-            if (sa == 0xffu) {  // the DFA's state after this delimiter byte varies: walk the chunk
-                uint32_t r8 = s_start * 8u;
-                for (int i = 0; i <= hb; ++i) r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
-                sa = r8 >> 3;
-            }
+            uint32_t r8 = s_start * 8u;
+            for (int i = 0; i <= hb; ++i) r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
+            s_last_sa = r8 >> 3;
         }
-        s_last_sa = sa;
+        __syncthreads();
+        my_last_sa = s_last_sa;
     }
-    if (len > 0 && c0 + len == tile_len) s_ctl_last = (uint32_t)((cmask >> (len - 1)) & 1u);
-    __syncthreads();
+    const uint32_t my_ctl_last =
+        tile_len > 0 ? (s_ctl[(tile_len - 1) >> 5] >> ((tile_len - 1) & 31)) & 1u : 0u;
 
     const int Ft = (int)tagg.nf, Rt = (int)tagg.nr;
     const bool staged = Ft <= FCAP && Rt <= RCAP;
@@ -867,10 +872,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const u64 a0 = ((u64)tagg.nr << 31) | tagg.nf;
     u64 a1;
     {
-        const uint32_t lastrel = tagg.last;  // position + 1, 0 = none
         const u64 colw = (tagg.col & kCAbs) ? ((1ull << 30) | (tagg.col & ~kCAbs)) : tagg.col;
-        u64 lastw = s_ctl_last ? (1ull << 29) : 0ull;
-        if (lastrel) lastw |= (1ull << 30) | ((u64)s_last_sa << 25) | (u64)(lastrel - 1);
+        u64 lastw = my_ctl_last ? (1ull << 29) : 0ull;
+        if (lastrel) lastw |= (1ull << 30) | ((u64)my_last_sa << 25) | (u64)(lastrel - 1);
         a1 = (colw << 31) | lastw;
     }
     if (tid == 0 && tile > 0) {
