@@ -47,7 +47,7 @@ class _OrcDfa(ctypes.Structure):
 class _OrcResult(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "status", "num_records", "num_fields", "first_invalid_offset", "final_state",
-        "num_conversion_errors", "num_ragged_records")]
+        "num_conversion_errors", "num_ragged_records", "min_record_fields", "max_record_fields")]
 
 
 _lib = None
@@ -95,6 +95,8 @@ class ParseResult:
     final_state: int
     num_conversion_errors: int
     num_ragged_records: int
+    min_record_fields: int          # fewest fields in a record, -1 without records
+    max_record_fields: int          # most fields in a record (the inferred column count)
     record_offsets: np.ndarray      # int64[R+1]
     field_offsets: np.ndarray       # int64[F+1]
     column_ids: np.ndarray          # int32[F]
@@ -163,6 +165,7 @@ def parse(buf, dfa, schema_types, cap_records: Optional[int] = None,
     F = min(res.num_fields, cap_fields)
     return ParseResult(res.status, res.num_records, res.num_fields, res.first_invalid_offset,
                        res.final_state, res.num_conversion_errors, res.num_ragged_records,
+                       res.min_record_fields, res.max_record_fields,
                        rec[:R + 1], fld[:F + 1], cid[:F],
                        [x[:R] if x is not None else None for x in values],
                        [x[:R] if x is not None else None for x in valid],

@@ -18,7 +18,10 @@
  * (Sec. 3.2). Each field is then converted to its column's type (Sec. 3.3),
  * empty fields take the column default (Sec. 4.3, default values), and a
  * transition into the invalid state or a non-accepting end state is reported
- * (Sec. 4.3, validating format).
+ * (Sec. 4.3, validating format). The fewest and most fields over all records
+ * are reported for inferring or validating the number of columns (Sec. 4.3):
+ * the largest count is the inferred column count, and equal counts mean
+ * every record has the same number of columns.
  *
  * Readings where the paper is silent (all listed in the design notes):
  *  - a final record without a trailing record delimiter still counts, and a
@@ -30,6 +33,8 @@
  *    leading and one trailing control symbol removed (the enclosing quotes);
  *  - ragged records: missing columns get value 0 with valid = 0, extra
  *    fields are kept in the field arrays and dropped from typed columns;
+ *  - a record's column count is its number of fields (a blank line is one
+ *    empty field); without records the fewest is -1 and the most 0;
  *  - numbers follow a strict grammar (no blanks, no locale); floats are the
  *    binary64 value nearest to the decimal, ties to even (strtod's result).
  */
@@ -184,6 +189,7 @@ typedef struct {
     int64_t** str_end;
     locale_t cloc;
     int64_t R, F, col, conv_errors, ragged;
+    int64_t min_fields, max_fields; /* over the records closed so far */
 } run_t;
 
 static void write_default(run_t* r, int64_t rec, int64_t c)
@@ -244,6 +250,8 @@ static void close_field(run_t* r, const uint8_t* buf, int64_t b, int64_t e,
     if (is_record) {
         int64_t nf = r->col + 1;
         if (nf != r->ncols) r->ragged++;
+        if (r->R == 0 || nf < r->min_fields) r->min_fields = nf;
+        if (nf > r->max_fields) r->max_fields = nf;
         for (int64_t c = nf; c < r->ncols; c++) write_default(r, r->R, c);
         r->R++;
         if (r->record_offsets && r->R <= r->cap_records) r->record_offsets[r->R] = r->F;
@@ -317,6 +325,8 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
     res->final_state = s;
     res->num_conversion_errors = r.conv_errors;
     res->num_ragged_records = r.ragged;
+    res->min_record_fields = r.R ? r.min_fields : -1;
+    res->max_record_fields = r.max_fields;
     if (r.R > cap_records || r.F > cap_fields) res->status = ORC_CAPACITY;
     else if (first_inv >= 0) res->status = ORC_INVALID_INPUT;
     else if (!((dfa->accept_mask >> s) & 1u)) res->status = ORC_NON_ACCEPTING_END;

@@ -27,6 +27,8 @@ typedef struct {
     int64_t final_state;
     int64_t num_conversion_errors;
     int64_t num_ragged_records;
+    int64_t min_record_fields; /* fewest fields in a record; -1 without records */
+    int64_t max_record_fields; /* most fields in a record; 0 without records */
 } orc_result;
 
 int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,

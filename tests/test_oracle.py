@@ -63,6 +63,8 @@ def test_ragged_example(dfa):
     assert list(r.str_end[1]) == ints(g["col1_end"])
     assert list(r.valid[1]) == ints(g["col1_valid"])
     assert r.num_ragged_records == int(g["num_ragged_records"])
+    assert r.min_record_fields == int(g["min_record_fields"])
+    assert r.max_record_fields == int(g["max_record_fields"])
 
 
 def _quoted():
@@ -268,6 +270,7 @@ def test_empty_and_edge_inputs():
     r = oracle.parse(b"", dfa, [D.INT64])
     assert (r.num_records, r.num_fields, r.status) == (0, 0, oracle.STATUS_OK)
     assert list(r.field_offsets) == [0] and list(r.record_offsets) == [0]
+    assert (r.min_record_fields, r.max_record_fields) == (-1, 0)
     # no trailing LF: the last record still counts; field_offsets[F] = n + 1
     r = oracle.parse(b"1,2", dfa, [D.INT64, D.INT64])
     assert list(r.field_offsets) == [0, 2, 4] and list(r.values[1]) == [2]
@@ -277,9 +280,34 @@ def test_empty_and_edge_inputs():
     # blank line: a record with one empty field
     r = oracle.parse(b"\n\n", dfa, [D.INT64])
     assert r.num_records == 2 and r.num_fields == 2 and list(r.field_offsets) == [0, 1, 2]
+    assert (r.min_record_fields, r.max_record_fields) == (1, 1)
     # extra fields are kept in the field arrays and dropped from typed output
     r = oracle.parse(b"1,2,3\n", dfa, [D.INT64])
     assert r.num_fields == 3 and r.num_ragged_records == 1 and list(r.values[0]) == [1]
+    assert (r.min_record_fields, r.max_record_fields) == (3, 3)
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_column_counts_against_csv_module(seed):
+    """Fewest and most fields per record (Sec. 4.3, inferring or validating
+    the number of columns) against Python's csv module on random RFC-4180
+    text: quoted fields with delimiters, line breaks and doubled quotes,
+    empty fields, blank lines, with and without a final line break."""
+    import csv
+    import io
+    rng = random.Random(seed)
+    pieces = ["", "7", "abc", '"x,y"', '"a\nb"', '"say ""hi"""', '""', "-1.5"]
+    recs = []
+    for _ in range(rng.randrange(1, 60)):
+        k = rng.choice([1, 1, 2, 3, 5, 8, 13]) if seed % 2 else rng.choice([4, 4, 4, 5])
+        recs.append(",".join(rng.choice(pieces) for _ in range(k)))
+    text = "\n".join(recs) + ("\n" if seed % 3 else "")
+    rows = list(csv.reader(io.StringIO(text, newline="")))
+    counts = [max(len(row), 1) for row in rows]  # the module gives [] for a blank line
+    r = oracle.parse(text.encode(), D.csv4(), [D.STRING] * 4)
+    assert r.status == oracle.STATUS_OK and r.num_records == len(rows)
+    assert (r.min_record_fields, r.max_record_fields) == (min(counts), max(counts))
+    assert r.num_ragged_records == sum(c != 4 for c in counts)
 
 
 # ---- conversions against Python's exact arithmetic -------------------------
