@@ -92,6 +92,13 @@ typedef struct {
     int64_t final_state;
     int64_t num_conversion_errors; /* non-empty numeric fields that failed to convert */
     int64_t num_ragged_records;    /* records whose field count differs from ncols */
+    /* Column counts for inferring or validating the number of columns
+     * (Sec. 4.3): the fewest and the most fields in any record (a record's
+     * fields include those beyond ncols; a blank line is one empty field).
+     * The most is the inferred column count; equal values mean every record
+     * has that many. Without records: -1 and 0. */
+    int64_t min_record_fields;
+    int64_t max_record_fields;
 } pp_result_t;
 
 /*

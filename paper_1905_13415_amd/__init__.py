@@ -69,7 +69,7 @@ class PpOptions(ctypes.Structure):
 
 
 RESULT_FIELDS = ("status", "num_records", "num_fields", "first_invalid_offset", "final_state",
-                 "num_conversion_errors", "num_ragged_records")
+                 "num_conversion_errors", "num_ragged_records", "min_record_fields", "max_record_fields")
 
 _lib = None
 
@@ -177,7 +177,7 @@ class Outputs:
     values: List[Optional[object]]
     valid: List[Optional[object]]
     str_end: List[Optional[object]]
-    result: "object"  # int64[7] on device
+    result: "object"  # int64[len(RESULT_FIELDS)] on device: pp_result_t
     types: List[int]
 
     def result_dict(self):
@@ -200,7 +200,7 @@ def alloc_outputs(types: Sequence[int], cap_records: int, cap_fields: int, devic
                    torch.empty(cap_records + 1, dtype=torch.int64, device=device),
                    torch.empty(cap_fields + 1, dtype=torch.int64, device=device),
                    torch.empty(max(cap_fields, 1), dtype=torch.int32, device=device),
-                   vals, valid, ends, torch.zeros(7, dtype=torch.int64, device=device), list(types))
+                   vals, valid, ends, torch.zeros(len(RESULT_FIELDS), dtype=torch.int64, device=device), list(types))
 
 
 def _ptr(t):

@@ -88,6 +88,8 @@ __global__ void batch_init(BatchParams bp, u64* words, size_t nwords)
         r->first_invalid_offset = -1;
         r->num_conversion_errors = 0;
         r->num_ragged_records = 0;
+        r->min_record_fields = -1;  // all ones: the unsigned minimum starts at its top
+        r->max_record_fields = 0;
         r->num_records = 0;
         r->num_fields = 0;
         r->final_state = a.start_state;

@@ -149,6 +149,20 @@ __device__ inline u64 shfl_down64(u64 v, int d)
     return ((u64)hi << 32) | lo;
 }
 
+__device__ inline u64 shfl_xor64(u64 v, int d)
+{
+    uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d);
+    uint32_t hi = (uint32_t)__shfl_xor((int)(uint32_t)(v >> 32), d);
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ inline u64 readlane64(u64 v, int l)  // l wavefront-uniform
+{
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, l);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), l);
+    return ((u64)hi << 32) | lo;
+}
+
 __device__ inline u64 readlane0_64(u64 v)
 {
     // the builtin returns a signed int: take each half as unsigned before
@@ -478,7 +492,7 @@ struct TileSmem {
     Cnt wcnt[NW];
     uint32_t anyctl, s0, fin, last_sa, guess;
     u64 pref[4];
-    u64 err, ragged;
+    u64 err, ragged, fmin, fmax;  // fmin/fmax: fewest/most fields of a record closed here
 };
 
 // A buffer's constants in LDS: the per-byte transition rows (built by the
@@ -547,6 +561,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     u64* const s_pref = sm.pref;
     u64& s_err = sm.err;
     u64& s_ragged = sm.ragged;
+    u64& s_fmin = sm.fmin;
+    u64& s_fmax = sm.fmax;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -557,6 +573,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         s_anyctl = 0;
         s_err = 0;
         s_ragged = 0;
+        s_fmin = ~0ull;
+        s_fmax = 0;
     }
     if constexpr (SETUP) tile_setup<NT, B, NS8>(p, sm);  // first read after the staging barrier
 
@@ -1007,6 +1025,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     };
 
     int64_t nerr = 0, nragged = 0;
+    u64 fmin = ~0ull, fmax = 0;  // over the records this thread closes
     if (staged) {
         {
             const int64_t roomf = p.cap_fields - F0;
@@ -1058,7 +1077,12 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             // the open record from the previous tile continues at column C0 (any
             // C0 >= 65535 is beyond every schema column)
             const uint32_t cf = lr ? 0u : (C0 < 65535 ? (uint32_t)C0 : 65535u);
-            if (g == 0 && lr < (uint32_t)Rt && cf + end1 - first != (uint32_t)ncols) ++nragged;
+            if (g == 0 && lr < (uint32_t)Rt) {  // the record's field count (exact C0)
+                const u64 nf = (lr ? 0ull : (u64)C0) + (end1 - first);
+                nragged += nf != (u64)ncols;
+                fmin = nf < fmin ? nf : fmin;
+                fmax = nf > fmax ? nf : fmax;
+            }
             const uint32_t cb = g * per;
             const uint32_t ce = cb + per < (uint32_t)ncols ? cb + per : (uint32_t)ncols;
             const bool st = lr < lr_cap;
@@ -1149,7 +1173,14 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 }
             }
         }
-        if (ncols == 0 && tid == 0) nragged = Rt;
+        if (ncols == 0) {  // no column groups above: count the records here
+            for (int k = tid; k < Rt; k += NT) {
+                const u64 nf = k ? (u64)(s_recend[k] - s_recend[k - 1]) : (u64)C0 + s_recend[0] + 1u;
+                nragged += nf != (u64)ncols;
+                fmin = nf < fmin ? nf : fmin;
+                fmax = nf > fmax ? nf : fmax;
+            }
+        }
     } else {
         // ---- 6'/7'. per-thread path: each thread closes the fields whose delimiter it holds
         uint32_t L = cex.nf;
@@ -1185,6 +1216,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             }
             if (isrec) {
                 if (col + 1 != ncols) ++nragged;
+                fmin = (u64)(col + 1) < fmin ? (u64)(col + 1) : fmin;
+                fmax = (u64)(col + 1) > fmax ? (u64)(col + 1) : fmax;
                 for (int64_t c = col + 1; c < ncols; ++c) store_missing(p, s_cols, (int)c, s_cols[c].type, rec);
                 if (rec + 1 <= p.cap_records) gptr(p.record_offsets)[rec + 1] = f + 1;
                 ++lr;
@@ -1199,10 +1232,36 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 
     if (nerr) atomicAdd(&s_err, (u64)nerr);
     if (nragged) atomicAdd(&s_ragged, (u64)nragged);
+    // Wavefront reduction of the field counts; the common case, every lane
+    // with records holding the same counts, takes no shuffles.
+    const u64 hasf = ballot(fmax != 0);
+    if (hasf) {
+        const int l0 = __ffsll((long long)hasf) - 1;
+        const u64 mn0 = readlane64(fmin, l0), mx0 = readlane64(fmax, l0);
+        if (ballot(fmax != 0 && (fmin != mn0 || fmax != mx0))) {
+#pragma unroll
+            for (int d = 32; d; d >>= 1) {
+                const u64 a = shfl_xor64(fmin, d), b = shfl_xor64(fmax, d);
+                fmin = a < fmin ? a : fmin;
+                fmax = b > fmax ? b : fmax;
+            }
+        } else {
+            fmin = mn0;
+            fmax = mx0;
+        }
+        if (lane == 0) {
+            atomicMin(&s_fmin, fmin);
+            atomicMax(&s_fmax, fmax);
+        }
+    }
     __syncthreads();
     if (tid == 0) {
         if (s_err) atomicAdd((u64*)&p.result->num_conversion_errors, s_err);  // rare: generic is fine
         if (s_ragged) atomicAdd((u64*)&p.result->num_ragged_records, s_ragged);
+        if (s_fmax) {  // results unused: no wait for the atomics before the workgroup ends
+            atomicMin((u64*)&p.result->min_record_fields, s_fmin);
+            atomicMax((u64*)&p.result->max_record_fields, s_fmax);
+        }
         if (tile == (uint32_t)p.num_tiles - 1) {
             const int64_t R = R0 + Rt, F = F0 + Ft;
             const uint32_t fin = s_final;

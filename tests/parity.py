@@ -29,7 +29,8 @@ def expected_result(ref):
     return {"status": ref.status, "num_records": ref.num_records, "num_fields": ref.num_fields,
             "first_invalid_offset": ref.first_invalid_offset, "final_state": ref.final_state,
             "num_conversion_errors": ref.num_conversion_errors,
-            "num_ragged_records": ref.num_ragged_records}
+            "num_ragged_records": ref.num_ragged_records,
+            "min_record_fields": ref.min_record_fields, "max_record_fields": ref.max_record_fields}
 
 
 def compare(ref, out, res, types, tag=""):

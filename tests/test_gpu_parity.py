@@ -5,7 +5,8 @@ shapes) with ragged tails; the edge cases cover empty input, inputs ending
 at and off tile boundaries, fields and quotes spanning tiles, tiles of
 nothing but delimiters or tiny records (the per-thread fallback path),
 invalid input, unterminated quotes, capacity, an unaligned input pointer,
-3- to 8-state DFAs, hard float conversions, and a tile's first field of each
+3- to 8-state DFAs, hard float conversions, the fewest and most fields per
+record (a 70,000-field record across tiles), and a tile's first field of each
 type beginning 0-71, 100 and 200 bytes before the tile.
 """
 import random
@@ -142,6 +143,25 @@ def test_ragged_and_extra_fields():
     data = ("\n".join(lines) + "\n").encode()
     assert_same(u8(data), D.csv4(), [D.INT64] * 6)
     assert_same(u8(data), D.csv4(), [])
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_column_counts(shape):
+    """Fewest and most fields per record: a 70,000-field record spanning
+    several tiles (its count needs the exact carried column), blank lines
+    (one field each) at tile starts, and uniform stretches."""
+    tile = (shape[0] * shape[1]) if shape else TILE
+    rnd = random.Random(11)
+    head = "1,2,3\n" * 3000 + "x," * 69999 + "y\n" + "7\n" + "4,5,6\n" * 2000
+    head += ",".join("9" for _ in range(rnd.randint(1, 9))) + "\n"
+    pad = -(len(head) + 1) % tile  # the blank line below begins a tile
+    data = u8((head + "a" * pad + "\n" + "\n" + "1,2,3\n" * 1000).encode())
+    assert (len(head) + pad + 1) % tile == 0
+    ref, out, res = assert_same(data, D.csv4(), [D.INT64] * 3, opts=opts_of(shape))
+    assert (res["min_record_fields"], res["max_record_fields"]) == (1, 70000)
+    uniform = u8(b"1,2,3\n" * 20000)
+    ref, out, res = assert_same(uniform, D.csv4(), [D.INT64] * 3, opts=opts_of(shape))
+    assert (res["min_record_fields"], res["max_record_fields"], res["num_ragged_records"]) == (3, 3, 0)
 
 
 # ---- random symbol soup over each dialect ------------------------------------------------
