@@ -112,3 +112,21 @@ def test_server_argument_errors_without_device():
     assert L.pp_server_submit(None, None, None) == -1
     assert L.pp_server_release(None, 1) == -1
     assert pp.lib().pp_status_str(-7) == b"larger than the device budget"
+
+
+def _struct_fields(header, name):
+    text = re.sub(r"/\*.*?\*/", "", open(header).read(), flags=re.S)
+    body = re.search(r"typedef struct\s*\{([^{}]*)\}\s*" + name + r"\s*;", text, flags=re.S).group(1)
+    return [(m.group(1), m.group(2)) for m in re.finditer(r"(\w+)\s+(\w+)\s*;", body)]
+
+
+def test_result_record_layout_matches_binding():
+    """The binding reads the device result record as int64 words named in
+    the header's order; the serving completion embeds the same record."""
+    fields = _struct_fields(os.path.join(ROOT, "include", "parparaw.h"), "pp_result_t")
+    assert all(t == "int64_t" for t, _ in fields)
+    assert tuple(n for _, n in fields) == pp.RESULT_FIELDS
+    assert ctypes.sizeof(pp.PpResult) == 8 * len(fields)
+    # the oracle reports the same outcomes under the same names
+    ofields = _struct_fields(os.path.join(ROOT, "oracle", "oracle.h"), "orc_result")
+    assert tuple(n for _, n in ofields) == pp.RESULT_FIELDS
