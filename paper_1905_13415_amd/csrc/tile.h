@@ -30,7 +30,9 @@
 //      type is wavefront-uniform and the stores into the typed column are
 //      contiguous. This takes the place of the paper's radix-sort partition
 //      by column tag: the (record, column) pair addresses the output slot
-//      directly.
+//      directly. The lanes of the first column group also count their
+//      record's fields, for the fewest and most fields per record (column
+//      count inference and validation, Sec. 4.3).
 // Tiles with more fields or records than the LDS staging holds take a
 // per-thread path for steps 6-7 that gives the same outputs.
 // The input is read from HBM once; per-symbol metadata never leaves the chip;
