@@ -570,7 +570,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const int lane = tid & 63;
     const int wave = tid >> 6;
 
-    __syncthreads();  // the previous tile of this workgroup is done with LDS
+    // No barrier first: a workgroup parses one tile, and its kernel's own
+    // barrier (after the ticket) precedes this; nothing written below is
+    // read before the staging barrier.
     if (tid == 0) {
         s_anyctl = 0;
         s_err = 0;
