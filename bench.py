@@ -10,8 +10,11 @@ preallocated. One step = one pp_parse call (all stages of the path).
 
 Prints one JSON line. ``value`` is the parse rate in GB/s of input (10^9 B/s,
 the paper's unit); ``roofline`` prices the dominant kernel's input+output
-bytes against the 8 TB/s HBM peak; ``cpu_baseline`` is the sequential oracle
-on the host, timed on the same buffer.
+bytes against the 8 TB/s HBM peak; ``copy_kernel_gbs`` is the library's own
+16-byte streaming copy over as many bytes (the practical ceiling);
+``cpu_baseline`` is the sequential oracle on the host, timed on the same
+buffer. ``--workload`` selects the other configurations (c1 latency, c3 text-
+heavy CSV, c4 batched, c5 serving).
 """
 import argparse
 import json
@@ -27,7 +30,11 @@ HBM_PEAK_GBS = 8000.0
 
 KERNEL_SOURCES = ["paper_1905_13415_amd/csrc/tile.h", "paper_1905_13415_amd/csrc/parse.hip",
                   "paper_1905_13415_amd/csrc/convert.h", "paper_1905_13415_amd/csrc/convert_fast.h"]
-TRAFFIC_FILE = "profiles/parse_tiles_c2_1GiB_traffic.json"
+# HBM byte counters of the dominant kernel per plain workload, from committed
+# rocprofv3 counter runs (not measured in this process)
+TRAFFIC_FILES = {"c2": "profiles/parse_tiles_c2_1GiB_traffic.json",
+                 "c3": "profiles/parse_tiles_c3_2GiB_traffic.json"}
+METRIC = "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency"
 
 
 def kernel_source_hash():
@@ -39,18 +46,39 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
+def measured_traffic(workload):
     """HBM bytes per launch of the dominant kernel from the committed
     counter runs (FETCH_SIZE, WRITE_SIZE, each scaled by a plain copy's
     reading), or None when the kernel sources changed since they were taken."""
+    path = TRAFFIC_FILES.get(workload)
+    if not path:
+        return None
     try:
-        with open(os.path.join(ROOT, TRAFFIC_FILE)) as f:
+        with open(os.path.join(ROOT, path)) as f:
             t = json.load(f)
     except (OSError, ValueError):
         return None
     if t.get("source_sha256") != kernel_source_hash():
         return None
     return t["fetch_bytes"] + t["write_bytes"]
+
+
+def host_cpu():
+    """CPU model and the number of cores visible to this process."""
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        avail = len(os.sched_getaffinity(0))
+    except AttributeError:
+        avail = os.cpu_count() or 1
+    return {"cpu_model": model, "nproc": avail, "cpu_count": os.cpu_count()}
 
 
 def output_bytes(R, F, types):
@@ -65,19 +93,55 @@ def output_bytes(R, F, types):
     return b
 
 
+def copy_ceiling_gbs(nbytes, dev, stream):
+    """Read+write GB/s of the library's 16-byte streaming copy kernel over
+    nbytes (half read, half written): the practical HBM ceiling."""
+    import torch
+
+    import paper_1905_13415_amd as pp
+    half = max(nbytes // 2 // 256 * 256, 1 << 20)
+    src = torch.empty(half, dtype=torch.uint8, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        pp.copy(dst, src, stream=stream)
+    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    c0.record(stream)
+    for _ in range(10):
+        pp.copy(dst, src, stream=stream)
+    c1.record(stream)
+    torch.cuda.synchronize()
+    gbs = 2 * half * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
+    del src, dst
+    return gbs
+
+
+PLAIN = {
+    "c2": {"nbytes": 1 << 30, "schema": "SCHEMA_C2",
+           "data": "synthetic (seeded numeric CSV shaped like the NYC taxi trips; no dataset used)",
+           "workload": "c2: 1 GiB numeric CSV, 18 columns (4 int64, 2 timestamp, 8 float64, 4 string), "
+                       "~130 B/record, csv4 DFA, plain single-buffer launch"},
+    "c3": {"nbytes": 1 << 31, "schema": "SCHEMA_C3",
+           "data": "synthetic (seeded text-heavy CSV shaped like the yelp reviews; no dataset used)",
+           "workload": "c3: 2 GiB text-heavy CSV, 9 columns (3 id strings, 3 int64, 1 date, 2 quoted free-text "
+                       "strings with embedded delimiters, LF and doubled quotes), ~700 B/record, csv4 DFA, "
+                       "plain single-buffer launch"},
+}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--nbytes", type=int, default=1 << 30)
+    ap.add_argument("--nbytes", type=int, default=0, help="input size of c2/c3 (0: the workload's own)")
     ap.add_argument("--bytes-per-thread", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many launches (for rocprofv3), no JSON")
-    ap.add_argument("--workload", choices=["c1", "c2", "c4", "c5"], default="c2",
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5"], default="c2",
                     help="c1: 10,000-record RFC-4180 CSV, latency of one plain launch; "
                          "c2: 1 GiB numeric CSV, plain launch (default); "
+                         "c3: 2 GiB text-heavy quoted CSV, plain launch; "
                          "c4: 4,096 mixed-dialect buffers, batched launch against plain launches; "
                          "c5: request loop over pinned host inputs, p50/p99 latency")
     ap.add_argument("--c5-requests", type=int, default=2000)
@@ -99,17 +163,23 @@ def main():
         return bench_c4(args)
     if args.workload == "c5":
         return bench_c5(args)
+    return bench_plain(args)
 
-    import numpy as np
+
+def bench_plain(args):
+    """One plain launch over a resident buffer (c2 or c3); one step = one
+    pp_parse call, every stage of the path."""
     import torch
 
     import datagen
     import paper_1905_13415_amd as pp
     from datagen import dialects as D
 
+    wl = PLAIN[args.workload]
+    nbytes = args.nbytes or wl["nbytes"]
     t0 = time.time()
-    g = datagen.c2(nbytes=args.nbytes)
-    types = D.SCHEMA_C2.types
+    g = datagen.c2(nbytes=nbytes) if args.workload == "c2" else datagen.c3(nbytes=nbytes)
+    types = getattr(D, wl["schema"]).types
     dfa = D.csv4()
     n = len(g.data)
     R = g.nrecords
@@ -128,12 +198,12 @@ def main():
         for _ in range(args.profile_steps):
             call.launch(stream)
         torch.cuda.synchronize()
-        # reference for the HBM byte counters: one device copy of exactly 2^30 bytes
+        # reference for the HBM byte counters: one streaming copy of exactly 2^30 bytes
         src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
+        pp.copy(dst, src, stream=stream)
         torch.cuda.synchronize()
-        print("[bench] profile launches done (plus one 1 GiB device copy)", file=sys.stderr, flush=True)
+        print("[bench] profile launches done (plus one 1 GiB streaming copy)", file=sys.stderr, flush=True)
         return
 
     for _ in range(args.warmup):
@@ -145,7 +215,8 @@ def main():
         sys.exit(1)
 
     # timed region: K launches bracketed by synchronisation, HIP events on the
-    # launch stream around every call
+    # launch stream around every call (a call is the init kernel, a few
+    # microseconds, and the parse kernel)
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
            for _ in range(args.steps)]
     torch.cuda.synchronize()
@@ -160,26 +231,15 @@ def main():
     ms_mean = sum(per) / len(per)
     ms_med = per[len(per) // 2]
 
-    # practical ceiling: a device-to-device copy of the same number of bytes
     outb = output_bytes(R, F, types)
     total_b = n + outb
-    src = torch.empty(total_b // 2, dtype=torch.uint8, device=dev)
-    dst = torch.empty_like(src)
-    for _ in range(3):
-        dst.copy_(src)
-    c0, c1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    c0.record(stream)
-    for _ in range(10):
-        dst.copy_(src)
-    c1.record(stream)
-    torch.cuda.synchronize()
-    copy_gbs = 2 * src.numel() * 10 / (c0.elapsed_time(c1) / 1e3) / 1e9
-    del src, dst
+    copy_gbs = copy_ceiling_gbs(total_b, dev, stream)
 
     in_gbs = n / (ms_mean / 1e3) / 1e9
     inout_gbs = total_b / (ms_mean / 1e3) / 1e9
+    default_size = nbytes == wl["nbytes"] and not args.bytes_per_thread
     line = {
-        "metric": "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency",
+        "metric": METRIC,
         "value": round(in_gbs, 2),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -190,10 +250,9 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "u8",
-        "data": "synthetic (seeded numeric CSV shaped like the NYC taxi trips; no dataset used)",
+        "data": wl["data"],
         "config": {
-            "workload": "c2: 1 GiB numeric CSV, 18 columns (4 int64, 2 timestamp, 8 float64, 4 string), "
-                        "~130 B/record, csv4 DFA, plain single-buffer launch",
+            "workload": wl["workload"],
             "bytes": n, "records": R, "fields": F,
             "bytes_per_thread": args.bytes_per_thread or 64, "block_threads": 512 if not args.bytes_per_thread else 256,
         },
@@ -202,14 +261,17 @@ def main():
         "input_gbs": round(in_gbs, 2),
         "in_out_gbs": round(inout_gbs, 2),
         "output_bytes": outb,
-        "d2d_copy_gbs": round(copy_gbs, 1),
+        "copy_kernel_gbs": round(copy_gbs, 1),
+        "frac_of_copy_kernel": round(inout_gbs / copy_gbs, 4),
         "roofline": {
             "bound": "hbm",
             "achieved": round(inout_gbs, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": round(inout_gbs / HBM_PEAK_GBS, 4),
-            "traffic": measured_traffic() if args.nbytes == 1 << 30 and not args.bytes_per_thread else None,
+            "traffic": measured_traffic(args.workload) if default_size else None,
+            "timing": "HIP events on the launch stream around each call, mean over the timed steps",
+            "traffic_source": TRAFFIC_FILES.get(args.workload) if default_size else None,
         },
     }
 
@@ -219,10 +281,10 @@ def main():
         ref = oracle.parse(g.data, dfa, types, cap_records=R, cap_fields=F)
         cpu_s = time.perf_counter() - t
         assert ref.num_records == R
-        line["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
-                                "kind": "oracle",
-                                "sample": f"the whole {n}-byte workload, one sequential oracle parse "
-                                          f"({cpu_s:.1f} s, outputs preallocated)"}
+        line["cpu_baseline"] = dict({"value": round(n / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
+                                     "kind": "oracle",
+                                     "sample": f"the whole {n}-byte workload, one sequential oracle parse "
+                                               f"({cpu_s:.1f} s, outputs preallocated)"}, **host_cpu())
     print(json.dumps(line), flush=True)
 
 
@@ -272,7 +334,7 @@ def bench_c1(args):
     med = per[len(per) // 2]
     outb = output_bytes(R, F, types)
     line = {
-        "metric": "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency",
+        "metric": METRIC,
         "value": round(n / (med / 1e6) / 1e9, 3),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -305,9 +367,10 @@ def bench_c1(args):
         for _ in range(reps):
             oracle.parse(g.data, dfa, types, cap_records=R, cap_fields=F)
         cpu_s = (time.perf_counter() - t) / reps
-        line["cpu_baseline"] = {"value": round(n / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-                                "sample": f"the whole {n}-byte workload, {reps} sequential oracle parses "
-                                          f"({cpu_s * 1e3:.2f} ms each)"}
+        line["cpu_baseline"] = dict({"value": round(n / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1,
+                                     "kind": "oracle",
+                                     "sample": f"the whole {n}-byte workload, {reps} sequential oracle parses "
+                                               f"({cpu_s * 1e3:.2f} ms each)"}, **host_cpu())
     print(json.dumps(line), flush=True)
 
 
@@ -447,7 +510,7 @@ def bench_c4(args):
     in_gbs = total / (b_ms / 1e3) / 1e9
     inout_gbs = (total + outb) / (b_ms / 1e3) / 1e9
     line = {
-        "metric": "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency",
+        "metric": METRIC,
         "value": round(in_gbs, 2),
         "unit": "GB/s",
         "n_gpus": 1,
@@ -507,16 +570,19 @@ def bench_c4(args):
         for i in pick:
             one(i)
         cpu1 = time.perf_counter() - t
-        cores = min(16, os.cpu_count() or 1)
+        # a pool over every core this process may use, at most 16 (a one-GPU
+        # share of the host)
+        cores = min(16, host_cpu()["nproc"])
         t = time.perf_counter()
         with ThreadPoolExecutor(cores) as ex:
             list(ex.map(one, pick))
         cpun = time.perf_counter() - t
-        line["cpu_baseline"] = {"value": round(acc / cpu1 / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
-                                "sample": f"the first {len(pick)} buffers of the batch ({acc} bytes), "
-                                          f"sequential oracle, one thread ({cpu1:.1f} s)",
-                                "pool": {"value": round(acc / cpun / 1e9, 4), "cores": cores,
-                                         "note": "same sample, one buffer per task"}}
+        line["cpu_baseline"] = dict({"value": round(acc / cpu1 / 1e9, 4), "unit": "GB/s", "cores": 1,
+                                     "kind": "oracle",
+                                     "sample": f"the first {len(pick)} buffers of the batch ({acc} bytes), "
+                                               f"sequential oracle, one thread ({cpu1:.1f} s)",
+                                     "pool": {"value": round(acc / cpun / 1e9, 4), "cores": cores,
+                                              "note": "same sample, one buffer per task"}}, **host_cpu())
     batch.close()
     print(json.dumps(line), flush=True)
 
@@ -620,7 +686,7 @@ def bench_c5(args):
         loads[str(rho)] = {"overlapped": run(arr, False), "serial": run(arr, True)}
         print(f"[bench] load {rho}: {loads[str(rho)]}", file=sys.stderr, flush=True)
     line = {
-        "metric": "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency",
+        "metric": METRIC,
         "value": closed["sustained_gbs"],
         "unit": "GB/s",
         "n_gpus": 1,

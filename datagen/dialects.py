@@ -215,6 +215,26 @@ def s8(delim: bytes = b" ") -> Dfa:
                start_state=0, accept=[0, 1, 5], invalid_state=7)
 
 
+def relabel(dfa: Dfa, perm: Sequence[int]) -> Dfa:
+    """The same automaton with its states renumbered: old state s becomes
+    perm[s]. Tables, start, invalid and accepting states are permuted
+    together, so every input is tagged exactly as before; only the state
+    numbers (the final state reported) change. Used to exercise start states
+    other than 0."""
+    k = dfa.num_states
+    assert sorted(perm) == list(range(k)), perm
+    inv = [0] * k
+    for s, t in enumerate(perm):
+        inv[t] = s
+    nxt = [[perm[row[inv[t]]] for t in range(k)] for row in dfa.next_state]
+    tg = [[row[inv[t]] for t in range(k)] for row in dfa.tag]
+    return Dfa(dfa.name + "~" + "".join(map(str, perm)), [dfa.state_names[inv[t]] for t in range(k)],
+               list(dfa.group_symbols), nxt, tg, start_state=perm[dfa.start_state],
+               accept=sorted(perm[a] for a in dfa.accept),
+               invalid_state=perm[dfa.invalid_state] if dfa.invalid_state != NO_STATE else NO_STATE,
+               group_of=dfa.group_of)
+
+
 @dataclass
 class Schema:
     types: List[int]

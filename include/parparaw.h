@@ -39,7 +39,7 @@ extern "C" {
 typedef int32_t pp_status_t;
 #define PP_OK 0
 #define PP_ERR_ARG (-1)         /* null pointer, negative size, bad option */
-#define PP_ERR_DFA (-2)         /* DFA out of range or invalid state not absorbing */
+#define PP_ERR_DFA (-2)         /* DFA out of range, invalid state not absorbing or = start */
 #define PP_ERR_SCHEMA (-3)      /* too many columns or unknown type */
 #define PP_ERR_WORKSPACE (-4)   /* workspace smaller than pp_workspace_size() */
 #define PP_ERR_HIP (-5)         /* a HIP launch failed */
@@ -72,7 +72,7 @@ typedef struct {
     int32_t num_states;    /* 1..PP_MAX_STATES */
     int32_t num_groups;    /* 1..PP_MAX_GROUPS */
     int32_t start_state;   /* state before the first byte */
-    int32_t invalid_state; /* -1: none; else it must be absorbing (all next = itself) */
+    int32_t invalid_state; /* -1: none; else absorbing (all next = itself) and not start_state */
     uint32_t accept_mask;  /* bit s set: ending in state s is accepted */
     uint8_t group_of[256]; /* symbol -> group */
     uint8_t next[16][16];  /* [group][state] -> next state */
@@ -162,6 +162,13 @@ pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
 
 /* Static text for a pp_status_t. */
 const char* pp_status_str(pp_status_t s);
+
+/* Device-to-device copy of n bytes with 16-byte nontemporal vector loads
+ * and stores (bytes at unaligned ends), asynchronous on stream. The ranges
+ * must not overlap (PP_ERR_ARG). It measures the practical HBM ceiling the
+ * parse kernels are priced against, and moves a partition's unfinished
+ * record in the streaming form. */
+pp_status_t pp_copy(void* d_dst, const void* d_src, size_t n, void* stream);
 
 /* ---- batched form ---------------------------------------------------------
  * Many independent buffers, each with its own DFA (dialect), schema and

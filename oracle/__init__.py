@@ -119,7 +119,8 @@ def count(buf, dfa):
     res = _OrcResult()
     rc = lib.orc_parse(a.ctypes.data, len(a), ctypes.byref(d), 0, None, 0, 0,
                        None, None, None, None, None, None, ctypes.byref(res))
-    assert rc == 0
+    if rc != 0:
+        raise ValueError("oracle: rejected arguments (a DFA that starts in its invalid state?)")
     return res.num_records, res.num_fields
 
 
@@ -160,7 +161,8 @@ def parse(buf, dfa, schema_types, cap_records: Optional[int] = None,
     rc = lib.orc_parse(a.ctypes.data, len(a), ctypes.byref(d), ncols, tarr.ctypes.data,
                        cap_records, cap_fields, rec.ctypes.data, fld.ctypes.data, cid.ctypes.data,
                        vptr, mptr, eptr, ctypes.byref(res))
-    assert rc == 0
+    if rc != 0:
+        raise ValueError("oracle: rejected arguments (a DFA that starts in its invalid state?)")
     R = min(res.num_records, cap_records)
     F = min(res.num_fields, cap_fields)
     return ParseResult(res.status, res.num_records, res.num_fields, res.first_invalid_offset,

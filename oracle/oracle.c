@@ -7,8 +7,8 @@
  *
  * What it computes is the plain definition that the parallel method reaches
  * exactly: one DFA instance started in the start state reads the input from
- * the first symbol to the last (Sec. 3.1: "a sequential approach would
- * simply set the starting state ... and read the symbols beginning to end").
+ * the first symbol to the last (the sequential baseline that Sec. 3.1 sets
+ * the parallel method against).
  * The multi-start-state simulation and the composition scan of Sec. 3.1 only
  * let that same run be split across threads, so they do not appear here.
  *
@@ -269,6 +269,9 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
               orc_result* res)
 {
     if (!dfa || !res || n < 0 || ncols < 0) return -1;
+    /* a run that starts in the invalid state has no transition into it to
+     * report (Sec. 4.3 flags the transition), so such a DFA is rejected */
+    if (dfa->invalid_state >= 0 && dfa->invalid_state == dfa->start_state) return -1;
     run_t r;
     memset(&r, 0, sizeof r);
     r.dfa = dfa;

@@ -10,13 +10,15 @@ from __future__ import annotations
 import ctypes
 import os
 import subprocess
+import threading
 from dataclasses import dataclass
 from typing import List, Optional, Sequence
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
-SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip")]
+BUILD_DIR = os.path.join(_ROOT, "_build")
 
 PP_OK = 0
 STATUS_TEXT = {0: "ok", -1: "invalid argument", -2: "invalid DFA", -3: "invalid schema",
@@ -27,20 +29,35 @@ INT64, FLOAT64, TIMESTAMP_S, DATE_DAYS, STRING, SKIP = 0, 1, 2, 3, 4, 5
 RESULT_OK, RESULT_INVALID_INPUT, RESULT_NON_ACCEPTING_END, RESULT_CAPACITY = 0, 1, 2, 3
 MAX_COLUMNS = 64
 
-HIPCC_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
-               "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
+COMPILE_FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
+                 "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
 
 def build(verbose: bool = False) -> str:
-    """Compile the HIP sources for gfx950 into libparparaw.so (in-tree)."""
+    """Compile the HIP sources for gfx950 (one hipcc per source, in
+    parallel) and link them into libparparaw.so (in-tree)."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    cmd = [hipcc] + HIPCC_FLAGS + ["-I", os.path.join(_ROOT, "include"),
-                                   "-I", os.path.join(_HERE, "csrc")] + SOURCES + ["-o", LIB_PATH + ".tmp"]
-    r = subprocess.run(cmd, capture_output=True, text=True)
+    os.makedirs(BUILD_DIR, exist_ok=True)
+    inc = ["-I", os.path.join(_ROOT, "include"), "-I", os.path.join(_HERE, "csrc")]
+    objs, procs = [], []
+    for src in SOURCES:
+        obj = os.path.join(BUILD_DIR, os.path.basename(src) + ".o")
+        objs.append(obj)
+        procs.append(subprocess.Popen([hipcc] + COMPILE_FLAGS + inc + ["-c", src, "-o", obj],
+                                      stdout=subprocess.PIPE, stderr=subprocess.PIPE, text=True))
+    errs = []
+    for src, pr in zip(SOURCES, procs):
+        out, err = pr.communicate()
+        if pr.returncode != 0:
+            errs.append(f"{src}:\n{out}{err}")
+        elif verbose:
+            print(err)
+    if errs:
+        raise RuntimeError("hipcc failed:\n" + "\n".join(errs))
+    r = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC"] + objs + ["-o", LIB_PATH + ".tmp"],
+                       capture_output=True, text=True)
     if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stdout + r.stderr)
-    if verbose:
-        print(r.stderr)
+        raise RuntimeError("hipcc link failed:\n" + r.stdout + r.stderr)
     os.replace(LIB_PATH + ".tmp", LIB_PATH)
     return LIB_PATH
 
@@ -117,6 +134,8 @@ def lib():
         L.pp_batch_autotune.restype = ctypes.c_int32
         L.pp_batch_autotune.argtypes = [P, ctypes.c_int32, P, ctypes.c_int32, P, ctypes.c_size_t, ctypes.c_int32,
                                         P, P, P]
+        L.pp_copy.restype = ctypes.c_int32
+        L.pp_copy.argtypes = [P, P, ctypes.c_size_t, P]
         L.pp_server_create.restype = ctypes.c_int32
         L.pp_server_create.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(P)]
         L.pp_server_submit.restype = ctypes.c_int32
@@ -241,6 +260,18 @@ class Call:
                             ctypes.c_void_p(stream.cuda_stream))
         if rc != PP_OK:
             raise PpError(f"pp_parse: {STATUS_TEXT.get(rc, rc)}")
+
+
+def copy(dst, src, nbytes: Optional[int] = None, stream=None) -> None:
+    """pp_copy: ``nbytes`` (default: all of ``src``) from device tensor
+    ``src`` to device tensor ``dst`` with the library's streaming copy."""
+    import torch
+    n = src.numel() * src.element_size() if nbytes is None else int(nbytes)
+    if n > dst.numel() * dst.element_size() or n > src.numel() * src.element_size():
+        raise PpError("pp_copy: byte count beyond a tensor")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    _check(lib().pp_copy(dst.data_ptr(), src.data_ptr(), n, ctypes.c_void_p(stream.cuda_stream)), "pp_copy")
 
 
 def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
@@ -464,6 +495,9 @@ class Server:
                "pp_server_create")
         self.handle = h
         self._live = {}  # id -> (pinned tensor, types array, types list) kept alive until completion
+        # a request can complete before its submit returns: submit records it
+        # under this lock, which poll takes too
+        self._lock = threading.Lock()
         self._buf = (PpServerCompletion * 256)()
 
     def submit(self, h_in, dialect: int, types: Sequence[int], cap_records: int, cap_fields: int) -> int:
@@ -474,19 +508,21 @@ class Server:
         rq = PpServerRequest(h_in.data_ptr() if n else None, n, dialect, nc, ctypes.cast(t, ctypes.c_void_p),
                              cap_records, cap_fields)
         rid = ctypes.c_uint64()
-        _check(lib().pp_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(rid)), "pp_server_submit")
-        self._live[rid.value] = (h_in, t, list(types))
+        with self._lock:
+            _check(lib().pp_server_submit(self.handle, ctypes.byref(rq), ctypes.byref(rid)), "pp_server_submit")
+            self._live[rid.value] = (h_in, t, list(types))
         return rid.value
 
     def poll(self, max_items: int = 256) -> List[Completion]:
-        arr = self._buf
+        arr = (PpServerCompletion * 256)()
         got = ctypes.c_int32()
         _check(lib().pp_server_poll(self.handle, arr, min(max_items, len(arr)), ctypes.byref(got)),
                "pp_server_poll")
         out = []
         for i in range(got.value):
             c = arr[i]
-            keep = self._live.pop(c.id, (None, None, []))
+            with self._lock:
+                keep = self._live.pop(c.id, (None, None, []))
             cc = PpServerCompletion.from_buffer_copy(c)
             out.append(Completion(c.id, c.n, {f: getattr(c.result, f) for f in RESULT_FIELDS},
                                   c.t_arrival_ns, c.t_admit_ns, c.t_h2d_done_ns, c.t_parse_done_ns,

@@ -110,6 +110,8 @@ static pp_status_t check_dfa(const pp_dfa_t* d)
     if (d->num_groups < 1 || d->num_groups > PP_MAX_GROUPS) return PP_ERR_DFA;
     if (d->start_state < 0 || d->start_state >= d->num_states) return PP_ERR_DFA;
     if (d->invalid_state < -1 || d->invalid_state >= d->num_states) return PP_ERR_DFA;
+    // a run that starts in the invalid state has no transition into it to report
+    if (d->invalid_state == d->start_state) return PP_ERR_DFA;
     for (int b = 0; b < 256; ++b)
         if (d->group_of[b] >= d->num_groups) return PP_ERR_DFA;
     for (int g = 0; g < d->num_groups; ++g)

@@ -1014,7 +1014,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             return (s_ctl[r >> 5] >> (r & 31)) & 1u;
         }
         const uint32_t by = b >= tile_start - kLdsBefore ? s_bytes[b - tile_start] : gptr(p.in)[b];
-        const uint32_t s8 = last_sa * 8u;
+        // b follows the last delimiter before the tile, or is the buffer's
+        // first byte (no delimiter before the tile), read in the start state
+        const uint32_t s8 = (last_has ? last_sa : (uint32_t)p.start_state) * 8u;
         uint32_t x;
         if constexpr (NS8) x = __builtin_amdgcn_ubfe(s_tcomb[2 * by + (s8 >> 5)], s8 & 31u, 8);
         else x = __builtin_amdgcn_ubfe(s_tcomb[by], s8, 8);

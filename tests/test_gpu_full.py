@@ -6,10 +6,13 @@ benchmark times.
   oracle element by element (every offset, column id, value and flag).
 - The 4,096-buffer batch (sizes log-uniform up to 64 MiB, 18 dialects, 23.7
   GB), parsed by one captured batched launch with the shape the autotuner
-  picks: every buffer's result record against the generator's record and
-  field counts, and a sample of buffers (the largest ones and an even
-  spread over the plan) against the oracle element by element.
+  picks: every buffer's result record against the generator's record,
+  field and column counts, and every buffer against the oracle element by
+  element.
 """
+import os
+from concurrent.futures import ThreadPoolExecutor
+
 import numpy as np
 import pytest
 
@@ -38,7 +41,7 @@ def test_full_text_2gib():
     assert ref.num_records == g.nrecords
 
 
-def test_full_batch_4096_buffers_sampled():
+def test_full_batch_4096_buffers():
     dfas = datagen.c4_dialects()
     plan = datagen.c4_plan()
     gens = [datagen.c4_buffer(spec) for spec in plan]
@@ -56,19 +59,28 @@ def test_full_batch_4096_buffers_sampled():
             arena[o:o + len(g.data)].copy_(torch.from_numpy(g.data))
         R, F = g.nrecords, g.nrecords * g.ncols
         items.append((arena[o:o + len(g.data)], spec.dialect, types, pp.alloc_outputs(types, R, F, device=dev)))
-        expect.append((R, F))
+        expect.append((R, F, g.ncols))
     best, _ = pp.autotune_batch(dfas, items, reps=1)
     batch = pp.Batch(dfas, items, opts=best)
     batch.capture()
     batch.replay()
     torch.cuda.synchronize()
     res = torch.stack([it[3].result for it in items]).cpu().numpy()
-    for i, (R, F) in enumerate(expect):
+    for i, (R, F, nc) in enumerate(expect):
         assert res[i, 0] == pp.RESULT_OK and res[i, 1] == R and res[i, 2] == F, (i, res[i].tolist())
-    order = sorted(range(len(plan)), key=lambda i: -sizes[i])
-    sample = sorted(set(order[:6]) | set(range(0, len(plan), 128)))
-    for i in sample:
+        if R:  # every generated record has the schema's column count
+            assert res[i, 7] == nc and res[i, 8] == nc, (i, res[i].tolist())
+
+    # every buffer element by element against the oracle, on a host thread
+    # pool (the oracle and the comparisons release the interpreter lock)
+    def check(i):
         d_in, dialect, types, out = items[i]
         ref = oracle.parse(gens[i].data, dfas[dialect], types)
         compare(ref, out, out.result_dict(), types, tag=f"buffer {i} ({sizes[i]} bytes, {dfas[dialect].name})")
+        return sizes[i]
+
+    workers = min(16, os.cpu_count() or 1)
+    with ThreadPoolExecutor(workers) as pool:
+        checked = sum(pool.map(check, range(len(plan))))
+    assert checked == sum(sizes)
     batch.close()

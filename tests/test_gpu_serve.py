@@ -148,3 +148,44 @@ def test_server_rejects_oversized_and_bad_requests():
     with pytest.raises(pp.PpError):
         srv.release(rid)  # already released by _drain
     srv.close()
+
+
+def test_server_c5_shaped_matches_oracle():
+    """The serving workload's shape: the log dialect (12 columns), request
+    sizes log-uniform from 4 KiB with several of 64-256 MiB among them,
+    Poisson arrivals overlapping the work in flight, a 2 GiB budget. Every
+    completion is compared with the oracle element by element."""
+    dfas = [D.log6()]
+    types = list(D.SCHEMA_LOG12.types)
+    rng = np.random.default_rng(190513419)
+    sizes = [int(np.exp(rng.uniform(np.log(4096), np.log(16 * MiB)))) for _ in range(28)]
+    for k, big in enumerate((64, 96, 160, 256)):
+        sizes.insert(3 + 7 * k, big * MiB)
+    reqs = [datagen.log(7000 + i, n).data for i, n in enumerate(sizes)]
+    assert max(len(d) for d in reqs) > 255 * MiB
+    pinned = [_pinned(d) for d in reqs]
+    arrivals = np.cumsum(rng.exponential(2e-3, len(reqs)))
+    srv = pp.Server(dfas, hbm_budget_bytes=2048 * MiB, max_slots=16, max_batch=8)
+    ids, got = {}, {}
+    t0 = time.time()
+    for i, (d, h) in enumerate(zip(reqs, pinned)):
+        while time.time() - t0 < arrivals[i]:  # arrivals overlap the work in flight
+            for c in srv.poll():
+                got[c.id] = (c, c.fetch())
+                srv.release(c.id)
+            time.sleep(2e-4)
+        # capacities from the request's byte count (log records average ~230
+        # bytes); a request that needs more is parsed again with exact sizes
+        cr = len(d) // 150 + 1
+        ids[srv.submit(h, 0, types, cr, 12 * cr)] = i
+    got.update(_drain(srv, len(reqs) - len(got), timeout_s=300))
+    assert sorted(ids) == sorted(got)
+    st = srv.stats()
+    assert st["completed"] == len(reqs) and st["arena_used_bytes"] == 0 and st["hip_error"] == 0
+    assert st["arena_peak_bytes"] <= st["arena_bytes"]
+    srv.close()
+    for rid, i in ids.items():
+        c, out = got[rid]
+        ref = oracle.parse(reqs[i], dfas[0], types)
+        assert c.result == expected_result(ref), f"request {i} ({len(reqs[i])} bytes)"
+        _same(out, _as_fetch(ref, types), f"request {i} ({len(reqs[i])} bytes)")

@@ -469,3 +469,54 @@ def test_generator_round_trip_mixed(name, delim, qstyle):
 def test_generator_round_trip_s8_log():
     g = datagen.log(9, 1 << 20, with_truth=True)
     _check_truth(g, D.s8(), D.SCHEMA_LOG12)
+
+
+# ---- start states other than 0 ---------------------------------------------------
+
+RELABEL = [("csv4", [2, 0, 3, 1]), ("paper6", [3, 5, 0, 1, 4, 2]), ("log6", [5, 3, 0, 1, 2, 4]),
+           ("s8", [6, 0, 1, 2, 3, 4, 5, 7]), ("s5", [1, 2, 3, 0, 4]), ("s3", [2, 1, 0])]
+
+
+@pytest.mark.parametrize("name,perm", RELABEL, ids=[r[0] for r in RELABEL])
+def test_relabelled_dfa_same_outputs(name, perm):
+    """Renumbering the states (start state no longer 0) changes no tag, so
+    every output except the final state's number is unchanged; a run that
+    took state 0 instead of the DFA's start state would differ here (a quoted
+    field at byte 0 would keep its opening quote)."""
+    base = D.ALL_DFAS[name]()
+    rel = D.relabel(base, perm)
+    assert rel.start_state != 0
+    alphabet = b"".join(base.group_symbols) + b"a1.-"
+    rnd = random.Random(7)
+    types = [D.STRING, D.INT64, D.FLOAT64, D.STRING]
+    quote = b'"' if b'"' in alphabet else (b"\\" if b"\\" in alphabet else b"")
+    texts = [b'"12",x\n', quote + b"7,a\nb" + quote + b",3\n"]
+    texts += [bytes(rnd.choice(alphabet) for _ in range(rnd.randint(0, 300))) for _ in range(200)]
+    for t in texts:
+        a = oracle.parse(t, base, types)
+        b = oracle.parse(t, rel, types)
+        assert b.final_state == perm[a.final_state]
+        for k in ("status", "num_records", "num_fields", "first_invalid_offset", "num_conversion_errors",
+                  "num_ragged_records", "min_record_fields", "max_record_fields"):
+            assert getattr(a, k) == getattr(b, k), (t, k)
+        for k in ("record_offsets", "field_offsets", "column_ids"):
+            np.testing.assert_array_equal(getattr(a, k), getattr(b, k))
+        for c in range(len(types)):
+            np.testing.assert_array_equal(a.values[c].view(np.int64), b.values[c].view(np.int64))
+            np.testing.assert_array_equal(a.valid[c], b.valid[c])
+
+
+def test_quoted_first_field_under_relabelled_csv4():
+    """Hand case: under csv4 with FB renumbered to 2, "12" at byte 0 is the
+    integer 12 (both quotes are control symbols read from the start state)."""
+    rel = D.relabel(D.csv4(), [2, 0, 3, 1])
+    r = oracle.parse(b'"12",x\n', rel, [D.INT64, D.STRING])
+    assert r.status == oracle.STATUS_OK and r.values[0].tolist() == [12] and r.valid[0].tolist() == [1]
+    assert (r.values[1].tolist(), r.str_end[1].tolist()) == ([5], [6])
+
+
+def test_start_in_invalid_state_rejected():
+    d = D.s5()
+    d.invalid_state = d.start_state
+    with pytest.raises(ValueError):
+        oracle.parse(b"1,2\n", d, [D.INT64])
