@@ -160,6 +160,28 @@ pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
                      void* d_ws, size_t ws_bytes, const pp_options_t* opts,
                      void* stream);
 
+/*
+ * pp_parse without a workspace argument, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation). Same arguments, outputs and errors as pp_parse,
+ * minus d_ws/ws_bytes: the workspace is a static array of
+ * PP_NOALLOC_SCRATCH_BYTES in the library's device code, one per GPU,
+ * resident until the process ends. Its device address is looked up on the
+ * first call on each device (the only set-up; nothing is allocated, by this
+ * call or later ones). Returns PP_ERR_WORKSPACE when the input needs more
+ * than that (pp_workspace_size(n, opts) > PP_NOALLOC_SCRATCH_BYTES: about
+ * 8 GiB of input at the default launch shape, 1 GiB at 256x16), PP_ERR_HIP
+ * if the address lookup fails.
+ * Every call on one GPU shares that GPU's array: calls that overlap in time
+ * on one GPU (other streams, other host threads) race and give wrong
+ * results; serialise them, e.g. on one stream. Calls on different GPUs are
+ * independent.
+ */
+#define PP_NOALLOC_SCRATCH_BYTES ((size_t)16 << 20)
+pp_status_t pp_parse_noalloc(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
+                             const pp_schema_t* schema, const pp_outputs_t* out,
+                             const pp_options_t* opts, void* stream);
+
 /* Static text for a pp_status_t. */
 const char* pp_status_str(pp_status_t s);
 

@@ -103,6 +103,8 @@ def lib():
         L.pp_workspace_size.argtypes = [ctypes.c_int64, P]
         L.pp_parse.restype = ctypes.c_int32
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_parse_noalloc.restype = ctypes.c_int32
+        L.pp_parse_noalloc.argtypes = [P, ctypes.c_int64, P, P, P, P, P]
         L.pp_status_str.restype = ctypes.c_char_p
         L.pp_status_str.argtypes = [ctypes.c_int32]
         L.pp_batch_create.restype = ctypes.c_int32
@@ -250,6 +252,19 @@ class Call:
         self.opts = opts
         self.out = out
 
+    def launch_noalloc(self, stream=None) -> None:
+        """The same call through pp_parse_noalloc (the library's static
+        per-device workspace; self.ws is not used)."""
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        rc = lib().pp_parse_noalloc(self.d_in.data_ptr() if self.n else None, self.n, ctypes.byref(self.dfa),
+                                    ctypes.byref(self.schema), ctypes.byref(self.outs),
+                                    ctypes.byref(self.opts) if self.opts else None,
+                                    ctypes.c_void_p(stream.cuda_stream))
+        if rc != PP_OK:
+            raise PpError(f"pp_parse_noalloc: {STATUS_TEXT.get(rc, rc)}")
+
     def launch(self, stream=None) -> None:
         import torch
         if stream is None:
@@ -285,6 +300,22 @@ def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
     call.launch(stream)
     out._call = call  # keep workspace alive until the caller synchronises
     return out
+
+
+def parse_noalloc(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
+                  opts: Optional[PpOptions] = None, stream=None) -> Outputs:
+    """Like parse(), through pp_parse_noalloc: the library's static
+    per-device workspace (NOALLOC_SCRATCH_BYTES), no workspace tensor.
+    Calls on one GPU must not overlap in time."""
+    n = int(d_in.numel())
+    out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device)
+    call = Call(d_in, n, dfa, types, out, None, opts)
+    call.launch_noalloc(stream)
+    out._call = call
+    return out
+
+
+NOALLOC_SCRATCH_BYTES = 16 << 20
 
 
 class PpBatchItem(ctypes.Structure):

@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cstring>
+#include <mutex>
 
 #include "parparaw.h"
 #include "tile.h"
@@ -220,6 +221,50 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     else launch_tiles<256, 16>(p, ns8, tiles, s);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
     return PP_OK;
+}
+
+// ---- entry point without allocation ---------------------------------------------
+// The workspace of pp_parse_noalloc: one static device array per GPU the
+// library runs on, held until the process ends. In host code `scratch` names
+// a host-side stand-in, never the device memory: its device address is taken
+// once per device (hipGetSymbolAddress, with that device current) and only
+// that address is passed to kernels. parse_init clears every part of it the
+// kernels read (tile ticket, lookback words; tables and column descriptors
+// are rewritten) with plain stores, so a call needs no memset and leaves no
+// state that the next call depends on.
+namespace pp {
+static __device__ __align__(256) uint8_t scratch[PP_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch[kMaxDevices];
+
+static pp_status_t scratch_of_current_device(void** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PP_ERR_HIP;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void* ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return PP_ERR_HIP;
+        g_scratch[dev] = ptr;
+    }
+    *out = g_scratch[dev];
+    return PP_OK;
+}
+}  // namespace pp
+
+extern "C" pp_status_t pp_parse_noalloc(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
+                                        const pp_schema_t* schema, const pp_outputs_t* out,
+                                        const pp_options_t* opts, void* stream)
+{
+    Shape sh;
+    if (n < 0 || !shape_of(opts, &sh)) return PP_ERR_ARG;
+    if (pp_workspace_size(n, opts) > PP_NOALLOC_SCRATCH_BYTES) return PP_ERR_WORKSPACE;
+    void* ws = nullptr;
+    const pp_status_t st = scratch_of_current_device(&ws);
+    if (st != PP_OK) return st;
+    return pp_parse(d_in, n, dfa, schema, out, ws, PP_NOALLOC_SCRATCH_BYTES, opts, stream);
 }
 
 extern "C" const char* pp_status_str(pp_status_t s)
