@@ -64,6 +64,8 @@ def _load():
         lib.orc_parse.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int64,
                                   ctypes.c_int64, P, P, P, P, P, P, P]
         lib.orc_conv.restype = ctypes.c_int
+        lib.orc_reject_ragged.restype = None
+        lib.orc_reject_ragged.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P, P, P, P]
         lib.orc_conv.argtypes = [ctypes.c_int32, P, ctypes.c_int64,
                                  ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_double)]
         _lib = lib
@@ -125,10 +127,12 @@ def count(buf, dfa):
 
 
 def parse(buf, dfa, schema_types, cap_records: Optional[int] = None,
-          cap_fields: Optional[int] = None) -> ParseResult:
+          cap_fields: Optional[int] = None, reject_ragged: bool = False) -> ParseResult:
     """Sequential parse of ``buf`` under ``dfa`` into the full output set.
 
-    With no capacities given, the exact sizes are counted first."""
+    With no capacities given, the exact sizes are counted first.
+    ``reject_ragged``: records whose field count differs from the schema's
+    column count lose their typed values (Sec. 4.3)."""
     lib = _load()
     a = _as_u8(buf)
     types = list(schema_types)
@@ -165,6 +169,8 @@ def parse(buf, dfa, schema_types, cap_records: Optional[int] = None,
         raise ValueError("oracle: rejected arguments (a DFA that starts in its invalid state?)")
     R = min(res.num_records, cap_records)
     F = min(res.num_fields, cap_fields)
+    if reject_ragged:
+        lib.orc_reject_ragged(ncols, tarr.ctypes.data, R, rec.ctypes.data, vptr, mptr, eptr)
     return ParseResult(res.status, res.num_records, res.num_fields, res.first_invalid_offset,
                        res.final_state, res.num_conversion_errors, res.num_ragged_records,
                        res.min_record_fields, res.max_record_fields,

@@ -338,6 +338,26 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
     return 0;
 }
 
+/* Rejecting the records that do not conform to the expected number of
+ * columns (Sec. 4.3, inferring or validating the number of columns): every
+ * record among the first R whose field count differs from ncols loses its
+ * typed values (value 0, valid 0, empty span in every column); its fields
+ * stay in the field arrays and in the counters. */
+void orc_reject_ragged(int32_t ncols, const int32_t* types, int64_t R, const int64_t* record_offsets,
+                       void** values, uint8_t** valid, int64_t** str_end)
+{
+    for (int64_t rec = 0; rec < R; rec++) {
+        if (record_offsets[rec + 1] - record_offsets[rec] == ncols) continue;
+        for (int32_t c = 0; c < ncols; c++) {
+            if (types[c] == TY_SKIP) continue;
+            if (types[c] == TY_FLOAT64) ((double*)values[c])[rec] = 0.0;
+            else ((int64_t*)values[c])[rec] = 0;
+            if (types[c] == TY_STRING) str_end[c][rec] = 0;
+            valid[c][rec] = 0;
+        }
+    }
+}
+
 /* Single conversions, exposed so that tests can pin them against Python's
  * int(), float() and calendar arithmetic on hand-picked cases. */
 int orc_conv(int32_t type, const uint8_t* p, int64_t len, int64_t* iv, double* dv)

@@ -310,6 +310,51 @@ def test_column_counts_against_csv_module(seed):
     assert r.num_ragged_records == sum(c != 4 for c in counts)
 
 
+def test_reject_ragged_hand_examples():
+    """Rejecting records whose column count differs from the schema's
+    (Sec. 4.3): their typed values become the defaults, their fields stay."""
+    t = b"1,Apples\n2\n"
+    keep = oracle.parse(t, D.csv4(), [D.INT64, D.STRING])
+    r = oracle.parse(t, D.csv4(), [D.INT64, D.STRING], reject_ragged=True)
+    assert list(keep.values[0]) == [1, 2] and list(keep.valid[0]) == [1, 1]
+    assert list(r.values[0]) == [1, 0] and list(r.valid[0]) == [1, 0]
+    assert list(r.values[1]) == [2, 0] and list(r.str_end[1]) == [8, 0] and list(r.valid[1]) == [1, 0]
+    assert list(r.field_offsets) == list(keep.field_offsets) and r.num_ragged_records == 1
+    t = b"a,b,c\nd,e\n"
+    r = oracle.parse(t, D.csv4(), [D.STRING, D.STRING], reject_ragged=True)
+    assert list(r.values[0]) == [0, 6] and list(r.str_end[0]) == [0, 7] and list(r.valid[0]) == [0, 1]
+    assert list(r.values[1]) == [0, 8] and list(r.str_end[1]) == [0, 9] and list(r.valid[1]) == [0, 1]
+    assert list(r.record_offsets) == [0, 3, 5] and list(r.column_ids) == [0, 1, 2, 0, 1]
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_reject_ragged_against_csv_module(seed):
+    """The records kept under rejection are exactly those Python's csv module
+    reads with four fields, and their string spans (quotes stripped, doubled
+    quotes undone) are the module's values."""
+    import csv
+    import io
+    rng = random.Random(100 + seed)
+    pieces = ["", "7", "abc", '"x,y"', '"a\nb"', '"say ""hi"""', '""', "-1.5"]
+    recs = [",".join(rng.choice(pieces) for _ in range(rng.choice([3, 4, 4, 4, 5])))
+            for _ in range(rng.randrange(5, 80))]
+    text = ("\n".join(recs) + "\n").encode()
+    rows = list(csv.reader(io.StringIO(text.decode(), newline="")))
+    r = oracle.parse(text, D.csv4(), [D.STRING] * 4, reject_ragged=True)
+    assert r.num_records == len(rows)
+    for i, row in enumerate(rows):
+        for c in range(4):
+            if len(row) != 4:
+                assert r.valid[c][i] == 0 and r.values[c][i] == 0 and r.str_end[c][i] == 0
+                continue
+            b, e = int(r.values[c][i]), int(r.str_end[c][i])
+            raw_begin = int(r.field_offsets[r.record_offsets[i] + c])
+            span = text[b:e].decode()
+            if text[raw_begin:raw_begin + 1] == b'"':
+                span = span.replace('""', '"')
+            assert r.valid[c][i] == 1 and span == row[c], (i, c)
+
+
 # ---- conversions against Python's exact arithmetic -------------------------
 
 INT_CASES = ["0", "-0", "+7", "123", "-123", "9223372036854775807", "-9223372036854775808",
