@@ -9,12 +9,15 @@
 //   [column descriptors of all buffers]
 //   [tile map: owning buffer of every (buffer, tile) work item]
 //   [lookback words: kWordsPerTile per work item]
-// A launch resets the counter, the lookback words and every buffer's result
-// record (batch_init), then runs batch_tiles with one workgroup per work item.
-// Work items are numbered buffer after buffer and tile after tile; a
-// workgroup takes the next ticket when it starts, so the tiles a work item
-// waits on in its buffer's lookback carry smaller tickets and belong to
-// workgroups that are already running.
+// A launch resets the counters, the lookback words and every buffer's result
+// record (batch_init), then runs batch_tiles with one workgroup per work item,
+// in two launches on the stream: buffers whose DFA has at most 4 states (one
+// v_perm_b32 and one table dword per byte) first, then the others (8-state
+// vectors). Work items are numbered buffer after buffer and tile after tile,
+// the first class's buffers before the second's; each launch has its own
+// ticket counter, and a workgroup takes the next ticket when it starts, so
+// the tiles a work item waits on in its buffer's lookback carry smaller
+// tickets and belong to workgroups that are already running.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -24,6 +27,7 @@
 #include <vector>
 
 #include "parparaw.h"
+#include "dfa_check.h"
 #include "tile.h"
 
 namespace pp {
@@ -34,9 +38,10 @@ struct BufDesc {
 };
 
 struct BatchParams {
-    unsigned int* counter;
+    unsigned int* counter;   // two ticket counters: <= 4-state launch, 8-state launch
     const BufDesc* bufs;
     const uint32_t* tilemap;
+    int64_t first_tile;      // work items [first_tile, first_tile + total_tiles) of this launch
     int64_t total_tiles;
     int32_t count;
 };
@@ -61,20 +66,21 @@ __device__ __forceinline__ T load_uniform(const T* p)
 // tiles of its buffer with smaller tickets, which are already running. (A
 // persistent loop over tickets was measured to raise register use from 105
 // to 176 VGPRs, halving occupancy, for no gain.)
-template <int NT, int B>
+template <int NT, int B, bool NS8>
 __global__ __launch_bounds__(NT) void batch_tiles(BatchParams bp)
 {
     __shared__ TileSmem<NT, B> sm;
     __shared__ uint32_t s_ticket;
-    if (threadIdx.x == 0) s_ticket = atomicAdd(bp.counter, 1u);
+    if (threadIdx.x == 0) s_ticket = atomicAdd(bp.counter + (NS8 ? 1 : 0), 1u);
     __syncthreads();
     // uniform across the workgroup: keep it (and the descriptor) in scalar registers
-    const uint32_t t = __builtin_amdgcn_readfirstlane(s_ticket);
-    if ((int64_t)t >= bp.total_tiles) return;
+    const uint32_t tk = __builtin_amdgcn_readfirstlane(s_ticket);
+    if ((int64_t)tk >= bp.total_tiles) return;
+    const int64_t t = bp.first_tile + (int64_t)tk;
     const uint32_t buf = __builtin_amdgcn_readfirstlane(bp.tilemap[t]);
     const BufDesc d = load_uniform(&bp.bufs[buf]);
-    const uint32_t local = (uint32_t)((int64_t)t - d.tile_base);
-    parse_tile<NT, B, true>(d.a, local, sm);  // 8-state vectors serve every dialect of the batch
+    const uint32_t local = (uint32_t)(t - d.tile_base);
+    parse_tile<NT, B, NS8>(d.a, local, sm);
 }
 
 __global__ void batch_init(BatchParams bp, u64* words, size_t nwords)
@@ -97,35 +103,21 @@ __global__ void batch_init(BatchParams bp, u64* words, size_t nwords)
         if (a.cap_records >= 0) a.record_offsets[0] = 0;
         if (a.cap_fields >= 0) a.field_offsets[0] = 0;
     }
-    if (i == 0) *bp.counter = 0u;
+    if (i == 0) {
+        bp.counter[0] = 0u;
+        bp.counter[1] = 0u;
+    }
 }
 
-// Host copies of pp_parse's checks and table construction (parse.hip keeps
-// its own; both follow the same table layout).
-static pp_status_t batch_check_dfa(const pp_dfa_t* d)
-{
-    if (!d) return PP_ERR_ARG;
-    if (d->num_states < 1 || d->num_states > PP_MAX_STATES) return PP_ERR_DFA;
-    if (d->num_groups < 1 || d->num_groups > PP_MAX_GROUPS) return PP_ERR_DFA;
-    if (d->start_state < 0 || d->start_state >= d->num_states) return PP_ERR_DFA;
-    if (d->invalid_state < -1 || d->invalid_state >= d->num_states) return PP_ERR_DFA;
-    // a run that starts in the invalid state has no transition into it to report
-    if (d->invalid_state == d->start_state) return PP_ERR_DFA;
-    for (int b = 0; b < 256; ++b)
-        if (d->group_of[b] >= d->num_groups) return PP_ERR_DFA;
-    for (int g = 0; g < d->num_groups; ++g)
-        for (int s = 0; s < d->num_states; ++s) {
-            if (d->next[g][s] >= d->num_states || d->tag[g][s] > PP_TAG_RECORD) return PP_ERR_DFA;
-            if (s == d->invalid_state && d->next[g][s] != s) return PP_ERR_DFA;
-        }
-    return PP_OK;
-}
+static pp_status_t batch_check_dfa(const pp_dfa_t* d) { return check_dfa_tables(d); }
 
 // Per-byte rows: next state of every state, and (next*8 | tag<<6) of every
-// state, one byte per state (Table 1's group rows expanded to bytes), in the
-// two-dword layout of 8-state vectors.
+// state, one byte per state (Table 1's group rows expanded to bytes): one
+// dword per byte for DFAs of at most 4 states, two (states 0-3, 4-7) for
+// larger ones.
 static void build_tables(const pp_dfa_t* d, uint32_t* t)
 {
+    const bool ns8 = d->num_states > 4;
     memset(t, 0, 1024 * sizeof(uint32_t));
     for (int b = 0; b < 256; ++b) {
         const int g = d->group_of[b];
@@ -138,10 +130,15 @@ static void build_tables(const pp_dfa_t* d, uint32_t* t)
             if (s < 4) { lo |= nx << (8 * s); clo |= cb << (8 * s); }
             else { hi |= nx << (8 * (s - 4)); chi |= cb << (8 * (s - 4)); }
         }
-        t[2 * b] = lo;  // 8-state layout for every dialect (see batch_tiles)
-        t[2 * b + 1] = hi;
-        t[512 + 2 * b] = clo;
-        t[512 + 2 * b + 1] = chi;
+        if (ns8) {
+            t[2 * b] = lo;
+            t[2 * b + 1] = hi;
+            t[512 + 2 * b] = clo;
+            t[512 + 2 * b + 1] = chi;
+        } else {
+            t[b] = lo;
+            t[512 + b] = clo;
+        }
     }
 }
 
@@ -153,6 +150,7 @@ struct pp_batch {
     int nt, b;
     int32_t count, ndfas;
     int64_t total_tiles;
+    int64_t tiles4;  // work items of buffers whose DFA has at most 4 states (numbered first)
     size_t off_tables, off_bufs, off_cols, off_map, off_words, ws_size;
     std::vector<pp_dfa_t> dfas;
     std::vector<BufDesc> bufs;     // device pointers filled in at bind
@@ -162,7 +160,6 @@ struct pp_batch {
     std::vector<uint32_t> tables;
     std::vector<char> blob;         // host image of the descriptor part of the workspace
     void* d_ws = nullptr;
-    int grid = 0;
 };
 
 struct pp_batch_graph {
@@ -247,12 +244,19 @@ extern "C" pp_status_t pp_batch_create(const pp_dfa_t* dfas, int32_t ndfas, cons
         a.start_state = d.start_state;
         a.invalid_state = d.invalid_state;
         a.accept_mask = d.accept_mask;
-        const int64_t nt_i = (it.n + tb - 1) / tb;
-        a.num_tiles = (int32_t)nt_i;
-        bd.tile_base = tiles;
-        tiles += nt_i;
+        a.num_tiles = (int32_t)((it.n + tb - 1) / tb);
         // the dialect index travels in the tables pointer, fixed up at bind
         a.tables = reinterpret_cast<const uint32_t*>((uintptr_t)it.dialect);
+    }
+    // work items: the buffers of <= 4-state DFAs first, then the others
+    for (int pass = 0; pass < 2; ++pass) {
+        for (int i = 0; i < count; ++i) {
+            BufDesc& bd = bt->bufs[i];
+            if ((bd.a.num_states > 4) != (pass == 1)) continue;
+            bd.tile_base = tiles;
+            tiles += bd.a.num_tiles;
+        }
+        if (pass == 0) bt->tiles4 = tiles;
     }
     // one workgroup per work item; the dispatch counts work-items in 32 bits
     if (tiles * nt > 0xffffffffll) { delete bt; return PP_ERR_UNSUPPORTED; }
@@ -303,9 +307,19 @@ extern "C" pp_status_t pp_batch_bind(pp_batch_t* bt, void* d_ws, size_t ws_bytes
     if (hipMemcpyAsync(d_ws, bt->blob.data(), bt->blob.size(), hipMemcpyHostToDevice, (hipStream_t)stream) !=
         hipSuccess)
         return PP_ERR_HIP;
-    bt->grid = (int)std::max<int64_t>(bt->total_tiles, 1);
     bt->d_ws = d_ws;
     return PP_OK;
+}
+
+template <bool NS8>
+static void launch_batch(const pp_batch_t* bt, const BatchParams& bp, hipStream_t s)
+{
+    const dim3 grid((unsigned)bp.total_tiles);
+    if (bt->nt == 512 && bt->b == 64) hipLaunchKernelGGL((batch_tiles<512, 64, NS8>), grid, dim3(512), 0, s, bp);
+    else if (bt->nt == 256 && bt->b == 64) hipLaunchKernelGGL((batch_tiles<256, 64, NS8>), grid, dim3(256), 0, s, bp);
+    else if (bt->nt == 256 && bt->b == 32) hipLaunchKernelGGL((batch_tiles<256, 32, NS8>), grid, dim3(256), 0, s, bp);
+    else if (bt->nt == 512 && bt->b == 32) hipLaunchKernelGGL((batch_tiles<512, 32, NS8>), grid, dim3(512), 0, s, bp);
+    else hipLaunchKernelGGL((batch_tiles<256, 16, NS8>), grid, dim3(256), 0, s, bp);
 }
 
 extern "C" pp_status_t pp_batch_launch(const pp_batch_t* bt, void* stream)
@@ -316,6 +330,7 @@ extern "C" pp_status_t pp_batch_launch(const pp_batch_t* bt, void* stream)
     bp.counter = (unsigned int*)ws;
     bp.bufs = (const BufDesc*)(ws + bt->off_bufs);
     bp.tilemap = (const uint32_t*)(ws + bt->off_map);
+    bp.first_tile = 0;
     bp.total_tiles = bt->total_tiles;
     bp.count = bt->count;
     hipStream_t s = (hipStream_t)stream;
@@ -324,14 +339,15 @@ extern "C" pp_status_t pp_batch_launch(const pp_batch_t* bt, void* stream)
     const int init_blocks = (int)std::min<size_t>(1024, std::max<size_t>(1, (work + 255) / 256));
     hipLaunchKernelGGL(batch_init, dim3(init_blocks), dim3(256), 0, s, bp, (u64*)(ws + bt->off_words), nwords);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
-    if (bt->total_tiles == 0) return PP_OK;
-    const dim3 grid((unsigned)bt->grid);
-    if (bt->nt == 512 && bt->b == 64) hipLaunchKernelGGL((batch_tiles<512, 64>), grid, dim3(512), 0, s, bp);
-    else if (bt->nt == 256 && bt->b == 64) hipLaunchKernelGGL((batch_tiles<256, 64>), grid, dim3(256), 0, s, bp);
-    else if (bt->nt == 256 && bt->b == 32) hipLaunchKernelGGL((batch_tiles<256, 32>), grid, dim3(256), 0, s, bp);
-    else if (bt->nt == 512 && bt->b == 32) hipLaunchKernelGGL((batch_tiles<512, 32>), grid, dim3(512), 0, s, bp);
-    else hipLaunchKernelGGL((batch_tiles<256, 16>), grid, dim3(256), 0, s, bp);
-    if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
+    // <= 4-state buffers, then the others (each launch only if it has work)
+    for (int cls = 0; cls < 2; ++cls) {
+        bp.first_tile = cls ? bt->tiles4 : 0;
+        bp.total_tiles = cls ? bt->total_tiles - bt->tiles4 : bt->tiles4;
+        if (bp.total_tiles == 0) continue;
+        if (cls == 0) launch_batch<false>(bt, bp, s);
+        else launch_batch<true>(bt, bp, s);
+        if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
+    }
     return PP_OK;
 }
 
