@@ -128,8 +128,17 @@ typedef struct {
     pp_result_t* d_result;
 } pp_outputs_t;
 
+/* Schema flags. PP_SCHEMA_REJECT_RAGGED: reject the records that do not
+ * conform to the expected number of columns (Sec. 4.3, validating the number
+ * of columns): a record whose field count differs from ncols gets the column
+ * defaults (value 0, valid 0, empty span) in every typed column; its fields
+ * stay in the offsets and column ids, and it is counted in
+ * num_ragged_records. */
+#define PP_SCHEMA_REJECT_RAGGED 1
+
 typedef struct {
     int32_t ncols;        /* 0..PP_MAX_COLUMNS */
+    int32_t flags;        /* PP_SCHEMA_* (0: none) */
     const int32_t* types; /* host array of ncols PP_* types */
 } pp_schema_t;
 
@@ -181,6 +190,19 @@ pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
 pp_status_t pp_parse_noalloc(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
                              const pp_schema_t* schema, const pp_outputs_t* out,
                              const pp_options_t* opts, void* stream);
+
+/*
+ * Inferring the number of columns without a schema (Sec. 4.3): d_in[0..n)
+ * is parsed for its structure only (no offsets, column ids or typed values
+ * are written) and *d_result receives the result record, whose
+ * max_record_fields is the inferred column count; min_record_fields ==
+ * max_record_fields tells that every record has it, and num_records /
+ * num_fields size the outputs of a following pp_parse. Status is never
+ * CAPACITY. d_ws as for pp_parse (pp_workspace_size(n, opts) bytes).
+ * Asynchronous on stream, no allocation.
+ */
+pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, pp_result_t* d_result,
+                             void* d_ws, size_t ws_bytes, const pp_options_t* opts, void* stream);
 
 /* Static text for a pp_status_t. */
 const char* pp_status_str(pp_status_t s);
@@ -327,6 +349,72 @@ pp_status_t pp_server_release(pp_server_t* server, uint64_t id);
 pp_status_t pp_server_get_stats(pp_server_t* server, pp_server_stats_t* stats);
 /* Waits for the device work in flight, then frees everything. */
 void pp_server_destroy(pp_server_t* server);
+
+/* ---- end-to-end streaming form (Sec. 4.4) -----------------------------------
+ * A host-resident input of any size parsed partition by partition: each
+ * partition's new bytes are copied to the device while the previous one is
+ * parsed and its columns are copied back, on separate streams. The record a
+ * partition leaves unfinished is carried over in front of the next
+ * partition's bytes (the carry-over region of Sec. 4.4), and the next
+ * transfer into a device buffer waits until that record has been moved out
+ * of it. A structure pass (no typed columns) finds where a partition's last
+ * complete record ends; the full parse then covers the complete records only,
+ * so every record is parsed once with its whole bytes. Outputs are rebased
+ * to global byte, field and record indices and written to host arrays.
+ * Outputs and result equal pp_parse's on the whole input, with two
+ * exceptions: a record longer than max_record_bytes fails the call
+ * (PP_ERR_UNSUPPORTED), and on invalid input the stream stops after the
+ * partition holding the first invalid transition (status INVALID_INPUT,
+ * first_invalid_offset exact; records up to that partition's last record
+ * delimiter are returned).
+ * The DFA must enter its start state after every record delimiter (a
+ * carried record restarts there); others get PP_ERR_DFA. */
+typedef struct {
+    int64_t partition_bytes;  /* new input bytes per partition (>= 4096; 0: 256 MiB) */
+    int64_t max_record_bytes; /* longest record that may span partitions (0: 16 MiB) */
+    int64_t cap_records;      /* device output capacity per partition (0: (P + M) / 32 + 1) */
+    int64_t cap_fields;       /* (0: (P + M) / 4 + 1) */
+    pp_options_t opts;        /* launch shape (zeros: default) */
+} pp_stream_config_t;
+
+/* Host output arrays, caller-allocated (pinned memory, hipHostMalloc, gives
+ * the full transfer rate), with the layout of pp_outputs_t. */
+typedef struct {
+    int64_t cap_records;
+    int64_t cap_fields;
+    int64_t* h_record_offsets;      /* [cap_records + 1] */
+    int64_t* h_field_offsets;       /* [cap_fields + 1] */
+    int32_t* h_column_ids;          /* [cap_fields] */
+    void* const* h_values;          /* per column, [cap_records] */
+    uint8_t* const* h_valid;
+    int64_t* const* h_str_end;
+} pp_host_outputs_t;
+
+typedef struct {
+    int64_t partitions;        /* full parses run */
+    int64_t structure_passes;  /* structure passes run (every partition but the last) */
+    int64_t carried_bytes;     /* bytes moved into the next partition's carry-over region */
+    int64_t max_carry;
+    int64_t bytes_returned;    /* offset bytes copied back (typed columns not counted) */
+} pp_stream_stats_t;
+
+typedef struct pp_stream pp_stream_t;
+
+/* Allocates the device buffers: two input buffers of max_record_bytes +
+ * partition_bytes, two output sets of the per-partition capacities and a
+ * workspace (the only allocations; parses allocate nothing). The DFA and
+ * schema are copied. */
+pp_status_t pp_stream_create(const pp_stream_config_t* cfg, const pp_dfa_t* dfa, const pp_schema_t* schema,
+                             pp_stream_t** stream);
+/* Parses h_in[0..n) (host memory; pinned gives the full rate) into the host
+ * outputs and returns when everything is back in host memory (*result
+ * holds the pp_result_t of the whole input; stats optional). Status
+ * CAPACITY in *result: a partition exceeded the device capacities or the
+ * input exceeded the host capacities (counts are those reached so far).
+ * One call at a time per stream object. */
+pp_status_t pp_stream_parse(pp_stream_t* stream, const uint8_t* h_in, int64_t n, const pp_host_outputs_t* out,
+                            pp_result_t* result, pp_stream_stats_t* stats);
+void pp_stream_destroy(pp_stream_t* stream);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,8 @@ from typing import List, Optional, Sequence
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
-SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip")]
+SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip",
+                                                     "stream.hip")]
 BUILD_DIR = os.path.join(_ROOT, "_build")
 
 PP_OK = 0
@@ -78,7 +79,10 @@ class PpOutputs(ctypes.Structure):
 
 
 class PpSchema(ctypes.Structure):
-    _fields_ = [("ncols", ctypes.c_int32), ("types", ctypes.c_void_p)]
+    _fields_ = [("ncols", ctypes.c_int32), ("flags", ctypes.c_int32), ("types", ctypes.c_void_p)]
+
+
+SCHEMA_REJECT_RAGGED = 1
 
 
 class PpOptions(ctypes.Structure):
@@ -103,6 +107,8 @@ def lib():
         L.pp_workspace_size.argtypes = [ctypes.c_int64, P]
         L.pp_parse.restype = ctypes.c_int32
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_infer_columns.restype = ctypes.c_int32
+        L.pp_infer_columns.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P, P]
         L.pp_parse_noalloc.restype = ctypes.c_int32
         L.pp_parse_noalloc.argtypes = [P, ctypes.c_int64, P, P, P, P, P]
         L.pp_status_str.restype = ctypes.c_char_p
@@ -138,6 +144,12 @@ def lib():
                                         P, P, P]
         L.pp_copy.restype = ctypes.c_int32
         L.pp_copy.argtypes = [P, P, ctypes.c_size_t, P]
+        L.pp_stream_create.restype = ctypes.c_int32
+        L.pp_stream_create.argtypes = [P, P, P, ctypes.POINTER(P)]
+        L.pp_stream_parse.restype = ctypes.c_int32
+        L.pp_stream_parse.argtypes = [P, P, ctypes.c_int64, P, P, P]
+        L.pp_stream_destroy.restype = None
+        L.pp_stream_destroy.argtypes = [P]
         L.pp_server_create.restype = ctypes.c_int32
         L.pp_server_create.argtypes = [P, P, ctypes.c_int32, ctypes.POINTER(P)]
         L.pp_server_submit.restype = ctypes.c_int32
@@ -233,13 +245,13 @@ class Call:
     objects alive so the same call can be issued repeatedly (benchmarks)."""
 
     def __init__(self, d_in, n: int, dfa, types: Sequence[int], out: Outputs, workspace,
-                 opts: Optional[PpOptions] = None):
+                 opts: Optional[PpOptions] = None, reject_ragged: bool = False):
         self.d_in = d_in
         self.n = n
         self.dfa = dfa_struct(dfa)
         nc = len(types)
         self.types = (ctypes.c_int32 * max(nc, 1))(*types)
-        self.schema = PpSchema(nc, ctypes.cast(self.types, ctypes.c_void_p))
+        self.schema = PpSchema(nc, SCHEMA_REJECT_RAGGED if reject_ragged else 0, ctypes.cast(self.types, ctypes.c_void_p))
         self.vptr = (ctypes.c_void_p * max(nc, 1))(*[_ptr(t) for t in out.values])
         self.mptr = (ctypes.c_void_p * max(nc, 1))(*[_ptr(t) for t in out.valid])
         self.eptr = (ctypes.c_void_p * max(nc, 1))(*[_ptr(t) for t in out.str_end])
@@ -290,16 +302,46 @@ def copy(dst, src, nbytes: Optional[int] = None, stream=None) -> None:
 
 
 def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
-          opts: Optional[PpOptions] = None, stream=None) -> Outputs:
-    """Parse the uint8 device tensor ``d_in`` (asynchronous on ``stream``)."""
+          opts: Optional[PpOptions] = None, stream=None, reject_ragged: bool = False) -> Outputs:
+    """Parse the uint8 device tensor ``d_in`` (asynchronous on ``stream``).
+    ``reject_ragged``: records whose field count differs from len(types)
+    get the column defaults in every typed column (Sec. 4.3)."""
     import torch
     n = int(d_in.numel())
     out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device)
     ws = torch.empty(max(workspace_size(n, opts), 1), dtype=torch.uint8, device=d_in.device)
-    call = Call(d_in, n, dfa, types, out, ws, opts)
+    call = Call(d_in, n, dfa, types, out, ws, opts, reject_ragged)
     call.launch(stream)
     out._call = call  # keep workspace alive until the caller synchronises
     return out
+
+
+def infer_columns(d_in, dfa, opts: Optional[PpOptions] = None, stream=None) -> dict:
+    """pp_infer_columns: the result record of a structure-only parse of the
+    uint8 device tensor ``d_in`` (Sec. 4.3): max_record_fields is the
+    inferred number of columns. Synchronises ``stream``."""
+    import torch
+    n = int(d_in.numel())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    res = torch.zeros(len(RESULT_FIELDS), dtype=torch.int64, device=d_in.device)
+    ws = torch.empty(max(workspace_size(n, opts), 1), dtype=torch.uint8, device=d_in.device)
+    d = dfa_struct(dfa)
+    _check(lib().pp_infer_columns(d_in.data_ptr() if n else None, n, ctypes.byref(d), res.data_ptr(), ws.data_ptr(),
+                                  ws.numel(), ctypes.byref(opts) if opts else None,
+                                  ctypes.c_void_p(stream.cuda_stream)), "pp_infer_columns")
+    stream.synchronize()
+    return dict(zip(RESULT_FIELDS, res.cpu().tolist()))
+
+
+def parse_schemaless(d_in, dfa, opts: Optional[PpOptions] = None, stream=None):
+    """Without a schema: the column count inferred by pp_infer_columns (the
+    most fields of any record), then pp_parse with that many string
+    columns. Returns (Outputs, result of the inference)."""
+    inf = infer_columns(d_in, dfa, opts, stream)
+    ncols = int(inf["max_record_fields"])
+    out = parse(d_in, dfa, [STRING] * ncols, inf["num_records"], inf["num_fields"], opts=opts, stream=stream)
+    return out, inf
 
 
 def parse_noalloc(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
@@ -403,6 +445,110 @@ class Batch:
             self.graph = None
         if self.handle:
             L.pp_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+# ---- end-to-end streaming form ---------------------------------------------------
+
+class PpStreamConfig(ctypes.Structure):
+    _fields_ = [("partition_bytes", ctypes.c_int64), ("max_record_bytes", ctypes.c_int64),
+                ("cap_records", ctypes.c_int64), ("cap_fields", ctypes.c_int64), ("opts", PpOptions)]
+
+
+class PpHostOutputs(ctypes.Structure):
+    _fields_ = [("cap_records", ctypes.c_int64), ("cap_fields", ctypes.c_int64),
+                ("h_record_offsets", ctypes.c_void_p), ("h_field_offsets", ctypes.c_void_p),
+                ("h_column_ids", ctypes.c_void_p), ("h_values", ctypes.c_void_p), ("h_valid", ctypes.c_void_p),
+                ("h_str_end", ctypes.c_void_p)]
+
+
+STREAM_STATS = ("partitions", "structure_passes", "carried_bytes", "max_carry", "bytes_returned")
+
+
+class PpStreamStats(ctypes.Structure):
+    _fields_ = [(f, ctypes.c_int64) for f in STREAM_STATS]
+
+
+@dataclass
+class HostOutputs:
+    """Host output arrays (torch CPU tensors, pinned when pin=True) of a
+    streamed parse, in the layout of Outputs."""
+    cap_records: int
+    cap_fields: int
+    record_offsets: "object"
+    field_offsets: "object"
+    column_ids: "object"
+    values: List[Optional[object]]
+    valid: List[Optional[object]]
+    str_end: List[Optional[object]]
+    types: List[int]
+    result: Optional[dict] = None
+    stats: Optional[dict] = None
+
+
+def alloc_host_outputs(types: Sequence[int], cap_records: int, cap_fields: int, pin: bool = True) -> HostOutputs:
+    import torch
+
+    def e(n, dt):
+        return torch.empty(max(n, 1), dtype=dt, pin_memory=pin)
+    vals, valid, ends = [], [], []
+    for ty in types:
+        if ty == SKIP:
+            vals.append(None); valid.append(None); ends.append(None)
+            continue
+        vals.append(e(cap_records, torch.float64 if ty == FLOAT64 else torch.int64))
+        valid.append(e(cap_records, torch.uint8))
+        ends.append(e(cap_records, torch.int64) if ty == STRING else None)
+    return HostOutputs(cap_records, cap_fields, e(cap_records + 1, torch.int64), e(cap_fields + 1, torch.int64),
+                       e(cap_fields, torch.int32), vals, valid, ends, list(types))
+
+
+class Stream:
+    """pp_stream_*: a host-resident input parsed partition by partition with
+    transfers, parsing and the return of the columns overlapped (Sec. 4.4)."""
+
+    def __init__(self, dfa, types: Sequence[int], partition_bytes: int = 0, max_record_bytes: int = 0,
+                 cap_records: int = 0, cap_fields: int = 0, opts: Optional[PpOptions] = None,
+                 reject_ragged: bool = False):
+        self._dfa = dfa_struct(dfa)
+        self.types = list(types)
+        nc = len(self.types)
+        self._types = (ctypes.c_int32 * max(nc, 1))(*self.types)
+        sch = PpSchema(nc, SCHEMA_REJECT_RAGGED if reject_ragged else 0, ctypes.cast(self._types, ctypes.c_void_p))
+        cfg = PpStreamConfig(partition_bytes, max_record_bytes, cap_records, cap_fields, opts or PpOptions())
+        h = ctypes.c_void_p()
+        _check(lib().pp_stream_create(ctypes.byref(cfg), ctypes.byref(self._dfa), ctypes.byref(sch), ctypes.byref(h)),
+               "pp_stream_create")
+        self.handle = h
+
+    def parse(self, h_in, out: HostOutputs) -> HostOutputs:
+        """Parse the uint8 host tensor ``h_in`` (pinned for the full rate)
+        into ``out``; returns ``out`` with ``result`` and ``stats`` set."""
+        n = int(h_in.numel())
+        nc = len(self.types)
+        vp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.values])
+        mp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.valid])
+        ep = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.str_end])
+        ho = PpHostOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets), _ptr(out.field_offsets),
+                           _ptr(out.column_ids), ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
+                           ctypes.cast(ep, ctypes.c_void_p))
+        res = PpResult()
+        st = PpStreamStats()
+        _check(lib().pp_stream_parse(self.handle, h_in.data_ptr() if n else None, n, ctypes.byref(ho),
+                                     ctypes.byref(res), ctypes.byref(st)), "pp_stream_parse")
+        out.result = {f: getattr(res, f) for f in RESULT_FIELDS}
+        out.stats = {f: getattr(st, f) for f in STREAM_STATS}
+        return out
+
+    def close(self):
+        if self.handle:
+            lib().pp_stream_destroy(self.handle)
             self.handle = None
 
     def __del__(self):

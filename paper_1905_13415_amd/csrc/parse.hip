@@ -9,6 +9,7 @@
 #include <mutex>
 
 #include "parparaw.h"
+#include "dfa_check.h"
 #include "tile.h"
 
 namespace pp {
@@ -104,30 +105,33 @@ static bool shape_of(const pp_options_t* o, Shape* s)
     return false;
 }
 
-static pp_status_t check_dfa(const pp_dfa_t* d)
-{
-    if (!d) return PP_ERR_ARG;
-    if (d->num_states < 1 || d->num_states > PP_MAX_STATES) return PP_ERR_DFA;
-    if (d->num_groups < 1 || d->num_groups > PP_MAX_GROUPS) return PP_ERR_DFA;
-    if (d->start_state < 0 || d->start_state >= d->num_states) return PP_ERR_DFA;
-    if (d->invalid_state < -1 || d->invalid_state >= d->num_states) return PP_ERR_DFA;
-    // a run that starts in the invalid state has no transition into it to report
-    if (d->invalid_state == d->start_state) return PP_ERR_DFA;
-    for (int b = 0; b < 256; ++b)
-        if (d->group_of[b] >= d->num_groups) return PP_ERR_DFA;
-    for (int g = 0; g < d->num_groups; ++g)
-        for (int s = 0; s < d->num_states; ++s) {
-            if (d->next[g][s] >= d->num_states || d->tag[g][s] > PP_TAG_RECORD) return PP_ERR_DFA;
-            if (s == d->invalid_state && d->next[g][s] != s) return PP_ERR_DFA;  // must absorb
-        }
-    return PP_OK;
-}
+static pp_status_t check_dfa(const pp_dfa_t* d) { return check_dfa_tables(d); }
 
 template <int NT, int B>
 static void launch_tiles(const Params& p, bool ns8, int64_t tiles, hipStream_t s)
 {
     if (ns8) hipLaunchKernelGGL((parse_tiles<NT, B, true>), dim3((unsigned)tiles), dim3(NT), 0, s, p);
     else hipLaunchKernelGGL((parse_tiles<NT, B, false>), dim3((unsigned)tiles), dim3(NT), 0, s, p);
+}
+
+// The typed values of the records whose field count differs from ncols
+// become the column defaults (records within the record capacity; the
+// record offsets give each record's field count).
+__global__ void reject_ragged(TileArgs a)
+{
+    const int64_t R0 = a.result->num_records;
+    const int64_t R = R0 < a.cap_records ? R0 : a.cap_records;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
+        if (a.record_offsets[r + 1] - a.record_offsets[r] == a.ncols) continue;
+        for (int c = 0; c < a.ncols; ++c) {
+            const ColDesc cd = a.cols[c];
+            if (cd.type == PP_SKIP) continue;
+            ((int64_t*)cd.values)[r] = 0;  // 0 and 0.0 share the bit pattern
+            cd.valid[r] = 0;
+            if (cd.type == PP_STRING) cd.str_end[r] = 0;
+        }
+    }
 }
 
 }  // namespace pp
@@ -143,9 +147,11 @@ extern "C" size_t pp_workspace_size(int64_t n, const pp_options_t* opts)
     return kWsHeader + kWsTables + kWsCols + (size_t)tiles * kWordsPerTile * sizeof(u64);
 }
 
-extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
-                                const pp_schema_t* schema, const pp_outputs_t* out, void* d_ws,
-                                size_t ws_bytes, const pp_options_t* opts, void* stream)
+// The parse behind pp_parse and pp_infer_columns (count_only: no outputs
+// beyond the result record, never CAPACITY).
+static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, const pp_schema_t* schema,
+                              const pp_outputs_t* out, void* d_ws, size_t ws_bytes, const pp_options_t* opts,
+                              void* stream, bool count_only)
 {
     if (n < 0 || (n > 0 && !d_in) || !schema || !out || !d_ws || !out->d_result) return PP_ERR_ARG;
     Shape sh;
@@ -158,6 +164,7 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     if (st != PP_OK) return st;
     if (schema->ncols < 0 || schema->ncols > PP_MAX_COLUMNS) return PP_ERR_SCHEMA;
     if (schema->ncols > 0 && !schema->types) return PP_ERR_SCHEMA;
+    if (schema->flags & ~PP_SCHEMA_REJECT_RAGGED) return PP_ERR_SCHEMA;
     if (ws_bytes < pp_workspace_size(n, opts)) return PP_ERR_WORKSPACE;
 
     Params p;
@@ -187,6 +194,7 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     a.start_state = dfa->start_state;
     a.invalid_state = dfa->invalid_state;
     a.accept_mask = dfa->accept_mask;
+    a.count_only = count_only ? 1 : 0;
     memcpy(p.group_of, dfa->group_of, 256);
     for (int g = 0; g < PP_MAX_GROUPS; ++g)
         for (int s = 0; s < PP_MAX_STATES; ++s) {
@@ -220,7 +228,34 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
     else if (sh.nt == 512 && sh.b == 32) launch_tiles<512, 32>(p, ns8, tiles, s);
     else launch_tiles<256, 16>(p, ns8, tiles, s);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
+    if ((schema->flags & PP_SCHEMA_REJECT_RAGGED) && schema->ncols > 0 && out->cap_records > 0) {
+        hipLaunchKernelGGL(reject_ragged, dim3(1024), dim3(256), 0, s, a);
+        if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
+    }
     return PP_OK;
+}
+
+extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa,
+                                const pp_schema_t* schema, const pp_outputs_t* out, void* d_ws,
+                                size_t ws_bytes, const pp_options_t* opts, void* stream)
+{
+    return parse_impl(d_in, n, dfa, schema, out, d_ws, ws_bytes, opts, stream, false);
+}
+
+extern "C" pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, pp_result_t* d_result,
+                                        void* d_ws, size_t ws_bytes, const pp_options_t* opts, void* stream)
+{
+    if (!d_ws || !d_result) return PP_ERR_ARG;
+    // no outputs: capacities 0; the first entries of the offset arrays,
+    // which the initialisation writes, go to spare words of the workspace
+    // header (its first word is the tile ticket)
+    pp_outputs_t o;
+    memset(&o, 0, sizeof o);
+    o.d_record_offsets = (int64_t*)((char*)d_ws + 128);
+    o.d_field_offsets = (int64_t*)((char*)d_ws + 192);
+    o.d_result = d_result;
+    pp_schema_t sch = {0, 0, nullptr};
+    return parse_impl(d_in, n, dfa, &sch, &o, d_ws, ws_bytes, opts, stream, true);
 }
 
 // ---- entry point without allocation ---------------------------------------------

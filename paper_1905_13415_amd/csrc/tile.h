@@ -111,6 +111,7 @@ struct TileArgs {
     int32_t start_state;
     int32_t invalid_state;
     uint32_t accept_mask;
+    int32_t count_only;  // no outputs but the result record, whose status is then never CAPACITY
 };
 
 
@@ -1272,7 +1273,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const int64_t R = R0 + Rt, F = F0 + Ft;
             const uint32_t fin = s_final;
             int64_t st;
-            if (R > p.cap_records || F > p.cap_fields) st = PP_RESULT_CAPACITY;
+            if (!p.count_only && (R > p.cap_records || F > p.cap_fields)) st = PP_RESULT_CAPACITY;
             else if (p.invalid_state >= 0 && fin == (uint32_t)p.invalid_state) st = PP_RESULT_INVALID_INPUT;
             else if (!((p.accept_mask >> fin) & 1u)) st = PP_RESULT_NON_ACCEPTING_END;
             else st = PP_RESULT_OK;

@@ -48,10 +48,10 @@ def test_workspace_size_and_status_text():
     assert pp.lib().pp_status_str(-2) == b"invalid DFA"
 
 
-def _call(dfa_struct, n=16, ncols=1, types=(0,), ws=1 << 20, in_ptr=0x1000, opts=None):
+def _call(dfa_struct, n=16, ncols=1, types=(0,), ws=1 << 20, in_ptr=0x1000, opts=None, flags=0):
     L = pp.lib()
     t = (ctypes.c_int32 * max(ncols, 1))(*types)
-    sch = pp.PpSchema(ncols, ctypes.cast(t, ctypes.c_void_p))
+    sch = pp.PpSchema(ncols, flags, ctypes.cast(t, ctypes.c_void_p))
     fake = ctypes.c_void_p(0x2000)
     ptrs = (ctypes.c_void_p * 64)(*([0x3000] * 64))
     out = pp.PpOutputs(4, 4, 0x4000, 0x5000, 0x6000, ctypes.cast(ptrs, ctypes.c_void_p),
@@ -76,6 +76,7 @@ def test_argument_errors_are_synchronous():
     assert _call(bad) == -2
     assert _call(good, ncols=65, types=[0] * 65) == -3
     assert _call(good, types=(9,)) == -3
+    assert _call(good, flags=2) == -3  # unknown schema flag
     assert _call(good, ws=8) == -4
     assert _call(good, n=-1) == -1
     assert _call(good, in_ptr=None) == -1
@@ -130,3 +131,30 @@ def test_result_record_layout_matches_binding():
     # the oracle reports the same outcomes under the same names
     ofields = _struct_fields(os.path.join(ROOT, "oracle", "oracle.h"), "orc_result")
     assert tuple(n for _, n in ofields) == pp.RESULT_FIELDS
+
+
+def test_stream_argument_errors_without_device():
+    """pp_stream_create validates before it allocates anything."""
+    L = pp.lib()
+    types = (ctypes.c_int32 * 2)(0, 0)
+    sch = pp.PpSchema(2, 0, ctypes.cast(types, ctypes.c_void_p))
+    h = ctypes.c_void_p()
+    cfg = pp.PpStreamConfig(1 << 20, 0, 0, 0, pp.PpOptions())
+    # a record delimiter that does not lead back to the start state: a record
+    # carried into the next partition could not restart there
+    bad = pp.dfa_struct(D.csv4())
+    bad.next[D.csv4().group_of[10]][0] = 1
+    assert L.pp_stream_create(ctypes.byref(cfg), ctypes.byref(bad), ctypes.byref(sch), ctypes.byref(h)) == -2
+    bad = pp.dfa_struct(D.csv4())
+    bad.start_state = 7
+    assert L.pp_stream_create(ctypes.byref(cfg), ctypes.byref(bad), ctypes.byref(sch), ctypes.byref(h)) == -2
+    good = pp.dfa_struct(D.csv4())
+    small = pp.PpStreamConfig(100, 0, 0, 0, pp.PpOptions())
+    assert L.pp_stream_create(ctypes.byref(small), ctypes.byref(good), ctypes.byref(sch), ctypes.byref(h)) == -1
+    badtypes = (ctypes.c_int32 * 2)(0, 9)
+    bsch = pp.PpSchema(2, 0, ctypes.cast(badtypes, ctypes.c_void_p))
+    assert L.pp_stream_create(ctypes.byref(cfg), ctypes.byref(good), ctypes.byref(bsch), ctypes.byref(h)) == -3
+    shape = pp.PpStreamConfig(1 << 20, 0, 0, 0, pp.options(48, 256))
+    assert L.pp_stream_create(ctypes.byref(shape), ctypes.byref(good), ctypes.byref(sch), ctypes.byref(h)) == -1
+    assert not h.value
+    assert L.pp_stream_parse(None, None, 0, None, None, None) == -1
