@@ -358,6 +358,44 @@ void orc_reject_ragged(int32_t ncols, const int32_t* types, int64_t R, const int
     }
 }
 
+/* A string column's materialised values (Sec. 3.3: a column's symbol string
+ * holds the fields' symbols without the control symbols): one sequential DFA
+ * run from the start state; every DATA symbol of a field in column `column`
+ * of a record r < cap_records is appended to record r's value. offsets[r] is
+ * where record r's value begins in chars, offsets[R'] (R' = min(R,
+ * cap_records)) the total length; chars beyond cap_chars are not written.
+ * A record without that column has an empty value. Returns the total. */
+int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t column, int64_t cap_records,
+                        int64_t* offsets, uint8_t* chars, int64_t cap_chars)
+{
+    int32_t s = dfa->start_state;
+    int64_t rec = 0, col = 0, total = 0;
+    int last_tag = -1;
+    if (cap_records >= 0 && offsets) offsets[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const int g = dfa->group_of[buf[i]];
+        const int t = dfa->tag[g][s];
+        s = dfa->next[g][s];
+        last_tag = t;
+        if (t == TAG_RECORD) {
+            rec++;
+            col = 0;
+            if (rec <= cap_records && offsets) offsets[rec] = total;
+        } else if (t == TAG_FIELD) {
+            col++;
+        } else if (t == TAG_DATA && col == column && rec < cap_records) {
+            if (chars && total < cap_chars) chars[total] = buf[i];
+            total++;
+        }
+    }
+    /* end of input closes the last record unless a record delimiter did */
+    if (n > 0 && last_tag != TAG_RECORD) {
+        rec++;
+        if (rec <= cap_records && offsets) offsets[rec] = total;
+    }
+    return total;
+}
+
 /* Single conversions, exposed so that tests can pin them against Python's
  * int(), float() and calendar arithmetic on hand-picked cases. */
 int orc_conv(int32_t type, const uint8_t* p, int64_t len, int64_t* iv, double* dv)

@@ -41,6 +41,9 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
 void orc_reject_ragged(int32_t ncols, const int32_t* types, int64_t R, const int64_t* record_offsets,
                        void** values, uint8_t** valid, int64_t** str_end);
 
+int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t column, int64_t cap_records,
+                        int64_t* offsets, uint8_t* chars, int64_t cap_chars);
+
 int orc_conv(int32_t type, const uint8_t* p, int64_t len, int64_t* iv, double* dv);
 
 #endif

@@ -355,6 +355,57 @@ def test_reject_ragged_against_csv_module(seed):
             assert r.valid[c][i] == 1 and span == row[c], (i, c)
 
 
+def test_materialize_quoted_example():
+    """The hand-worked quoted example: control symbols (enclosing quotes and
+    the first quote of a doubled pair) leave the values."""
+    g = read_golden("quoted_example.txt")
+    data = bytes.fromhex(g["input_hex"])
+    for c in (0, 1):
+        want = [bytes.fromhex(h) for h in g[f"materialized_col{c}_hex"].split("|")]
+        for dfa in (D.paper6(), D.csv4()):
+            offs, chars = oracle.materialize(data, dfa, c)
+            got = [bytes(chars[offs[r]:offs[r + 1]]) for r in range(len(offs) - 1)]
+            assert got == want, (c, dfa.name)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_materialize_against_csv_module(seed):
+    """Materialised values of every column equal Python's csv module's
+    fields on random RFC-4180 text (empty for records without the column)."""
+    import csv
+    import io
+    rng = random.Random(200 + seed)
+    pieces = ["", "7", "abc", '"x,y"', '"a\nb"', '"say ""hi"""', '""', '""""', "-1.5", "z z"]
+    recs = [",".join(rng.choice(pieces) for _ in range(rng.choice([1, 2, 3, 4, 4, 6])))
+            for _ in range(rng.randrange(5, 80))]
+    text = ("\n".join(recs) + ("\n" if seed % 2 else "")).encode()
+    rows = list(csv.reader(io.StringIO(text.decode(), newline="")))
+    for c in range(6):
+        offs, chars = oracle.materialize(text, D.csv4(), c)
+        assert len(offs) == len(rows) + 1
+        for r, row in enumerate(rows):
+            want = row[c] if c < len(row) else ""
+            assert bytes(chars[offs[r]:offs[r + 1]]).decode() == want, (seed, c, r)
+
+
+def test_materialize_log_escapes():
+    """The log dialect: backslash escapes inside quotes keep the escaped
+    character, brackets enclose a field with spaces; checked against a
+    regular-expression decoder of the same format."""
+    import re
+    rng = random.Random(5)
+    lines, want = [], []
+    for _ in range(200):
+        req = "".join(rng.choice(['a', ' ', '\\"', '\\\\', 'x', '/']) for _ in range(rng.randrange(0, 12)))
+        lines.append(f'h{rng.randrange(9)} [d t] "{req}" 200')
+        want.append(re.sub(r'\\(.)', r'\1', req))
+    text = ("\n".join(lines) + "\n").encode()
+    offs, chars = oracle.materialize(text, D.log6(), 2)
+    assert [bytes(chars[offs[r]:offs[r + 1]]).decode() for r in range(len(lines))] == want
+    offs, chars = oracle.materialize(text, D.log6(), 1)
+    assert all(bytes(chars[offs[r]:offs[r + 1]]) == b"d t" for r in range(len(lines)))
+
+
 # ---- conversions against Python's exact arithmetic -------------------------
 
 INT_CASES = ["0", "-0", "+7", "123", "-123", "9223372036854775807", "-9223372036854775808",
