@@ -126,6 +126,10 @@ typedef struct {
     uint8_t* const* d_valid;
     int64_t* const* d_str_end;
     pp_result_t* d_result;
+    /* Optional (NULL: not written): the control-symbol bitmap, bit i%32 of
+     * word i/32 set when byte i is a control symbol ((n + 31) / 32 words);
+     * pp_materialize_strings reads it. */
+    uint32_t* d_control_bitmap;
 } pp_outputs_t;
 
 /* Schema flags. PP_SCHEMA_REJECT_RAGGED: reject the records that do not
@@ -203,6 +207,28 @@ pp_status_t pp_parse_noalloc(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa
  */
 pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, pp_result_t* d_result,
                              void* d_ws, size_t ws_bytes, const pp_options_t* opts, void* stream);
+
+/*
+ * Materialised string column (Sec. 3.3: a column's symbol string without its
+ * control symbols). After pp_parse of d_in[0..n) with `parsed` as its
+ * outputs, d_control_bitmap given, and the work of that parse ordered before
+ * this call (e.g. the same stream): string column `column`'s values -- the
+ * bytes of each record's span that are not control symbols (so enclosing
+ * quotes, the first quote of a doubled pair and escape characters are
+ * removed) -- back to back in d_chars, the Arrow large-string layout:
+ * d_offsets[r] is where record r's value begins and d_offsets[R'] the total
+ * length, R' = min(num_records, cap_records) (d_offsets holds cap_records + 1
+ * entries). A record without the column, or rejected, has an empty value.
+ * Bytes beyond cap_chars are not written (compare d_offsets[R'] with it).
+ * Fields of any length are split over many wavefronts. d_ws: device scratch
+ * of pp_materialize_workspace_size(n, cap_records) bytes. Asynchronous on
+ * stream; no allocation. PP_ERR_ARG if the bitmap or the column's span
+ * arrays are missing.
+ */
+size_t pp_materialize_workspace_size(int64_t n, int64_t cap_records);
+pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed, int32_t column,
+                                   int64_t* d_offsets, uint8_t* d_chars, int64_t cap_chars, void* d_ws,
+                                   size_t ws_bytes, void* stream);
 
 /* Static text for a pp_status_t. */
 const char* pp_status_str(pp_status_t s);

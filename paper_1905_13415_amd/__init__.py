@@ -18,7 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip",
-                                                     "stream.hip")]
+                                                     "stream.hip", "materialize.hip")]
 BUILD_DIR = os.path.join(_ROOT, "_build")
 
 PP_OK = 0
@@ -75,7 +75,7 @@ class PpOutputs(ctypes.Structure):
                 ("d_record_offsets", ctypes.c_void_p), ("d_field_offsets", ctypes.c_void_p),
                 ("d_column_ids", ctypes.c_void_p), ("d_values", ctypes.c_void_p),
                 ("d_valid", ctypes.c_void_p), ("d_str_end", ctypes.c_void_p),
-                ("d_result", ctypes.c_void_p)]
+                ("d_result", ctypes.c_void_p), ("d_control_bitmap", ctypes.c_void_p)]
 
 
 class PpSchema(ctypes.Structure):
@@ -107,6 +107,11 @@ def lib():
         L.pp_workspace_size.argtypes = [ctypes.c_int64, P]
         L.pp_parse.restype = ctypes.c_int32
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_materialize_workspace_size.restype = ctypes.c_size_t
+        L.pp_materialize_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64]
+        L.pp_materialize_strings.restype = ctypes.c_int32
+        L.pp_materialize_strings.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, P, ctypes.c_int64, P,
+                                             ctypes.c_size_t, P]
         L.pp_infer_columns.restype = ctypes.c_int32
         L.pp_infer_columns.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P, P]
         L.pp_parse_noalloc.restype = ctypes.c_int32
@@ -212,13 +217,17 @@ class Outputs:
     str_end: List[Optional[object]]
     result: "object"  # int64[len(RESULT_FIELDS)] on device: pp_result_t
     types: List[int]
+    control_bitmap: Optional[object] = None  # int32[(n + 31) // 32]: control symbols, when requested
 
     def result_dict(self):
         r = self.result.cpu().tolist()
         return dict(zip(RESULT_FIELDS, r))
 
 
-def alloc_outputs(types: Sequence[int], cap_records: int, cap_fields: int, device="cuda") -> Outputs:
+def alloc_outputs(types: Sequence[int], cap_records: int, cap_fields: int, device="cuda",
+                  bitmap_bytes: int = -1) -> Outputs:
+    """Device outputs; bitmap_bytes >= 0 also allocates the control-symbol
+    bitmap of an input of that many bytes (for materialize())."""
     import torch
     vals, valid, ends = [], [], []
     for ty in types:
@@ -233,7 +242,9 @@ def alloc_outputs(types: Sequence[int], cap_records: int, cap_fields: int, devic
                    torch.empty(cap_records + 1, dtype=torch.int64, device=device),
                    torch.empty(cap_fields + 1, dtype=torch.int64, device=device),
                    torch.empty(max(cap_fields, 1), dtype=torch.int32, device=device),
-                   vals, valid, ends, torch.zeros(len(RESULT_FIELDS), dtype=torch.int64, device=device), list(types))
+                   vals, valid, ends, torch.zeros(len(RESULT_FIELDS), dtype=torch.int64, device=device), list(types),
+                   torch.empty(max((bitmap_bytes + 31) // 32, 1), dtype=torch.int32, device=device)
+                   if bitmap_bytes >= 0 else None)
 
 
 def _ptr(t):
@@ -259,7 +270,7 @@ class Call:
                               _ptr(out.field_offsets), _ptr(out.column_ids),
                               ctypes.cast(self.vptr, ctypes.c_void_p),
                               ctypes.cast(self.mptr, ctypes.c_void_p),
-                              ctypes.cast(self.eptr, ctypes.c_void_p), _ptr(out.result))
+                              ctypes.cast(self.eptr, ctypes.c_void_p), _ptr(out.result), _ptr(out.control_bitmap))
         self.ws = workspace
         self.opts = opts
         self.out = out
@@ -302,13 +313,14 @@ def copy(dst, src, nbytes: Optional[int] = None, stream=None) -> None:
 
 
 def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
-          opts: Optional[PpOptions] = None, stream=None, reject_ragged: bool = False) -> Outputs:
+          opts: Optional[PpOptions] = None, stream=None, reject_ragged: bool = False,
+          control_bitmap: bool = False) -> Outputs:
     """Parse the uint8 device tensor ``d_in`` (asynchronous on ``stream``).
     ``reject_ragged``: records whose field count differs from len(types)
     get the column defaults in every typed column (Sec. 4.3)."""
     import torch
     n = int(d_in.numel())
-    out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device)
+    out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device, bitmap_bytes=n if control_bitmap else -1)
     ws = torch.empty(max(workspace_size(n, opts), 1), dtype=torch.uint8, device=d_in.device)
     call = Call(d_in, n, dfa, types, out, ws, opts, reject_ragged)
     call.launch(stream)
@@ -342,6 +354,37 @@ def parse_schemaless(d_in, dfa, opts: Optional[PpOptions] = None, stream=None):
     ncols = int(inf["max_record_fields"])
     out = parse(d_in, dfa, [STRING] * ncols, inf["num_records"], inf["num_fields"], opts=opts, stream=stream)
     return out, inf
+
+
+def materialize(d_in, out: Outputs, column: int, cap_chars: Optional[int] = None, stream=None):
+    """pp_materialize_strings: string column ``column`` of a parse of the
+    device tensor ``d_in`` into ``out`` (parsed with control_bitmap=True)
+    with every control symbol removed, as device tensors (offsets int64
+    [cap_records + 1], chars uint8[cap_chars]). cap_chars defaults to the
+    input size (a value is never longer than its span). Asynchronous."""
+    import torch
+    n = int(d_in.numel())
+    if out.control_bitmap is None:
+        raise PpError("materialize: the parse did not write the control-symbol bitmap")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    cap_chars = n if cap_chars is None else int(cap_chars)
+    offsets = torch.empty(out.cap_records + 1, dtype=torch.int64, device=d_in.device)
+    chars = torch.empty(max(cap_chars, 1), dtype=torch.uint8, device=d_in.device)
+    ws = torch.empty(max(int(lib().pp_materialize_workspace_size(n, out.cap_records)), 1), dtype=torch.uint8,
+                     device=d_in.device)
+    nc = len(out.types)
+    vp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.values])
+    mp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.valid])
+    ep = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.str_end])
+    po = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets), _ptr(out.field_offsets),
+                   _ptr(out.column_ids), ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
+                   ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result), _ptr(out.control_bitmap))
+    _check(lib().pp_materialize_strings(d_in.data_ptr() if n else None, n, ctypes.byref(po), column,
+                                        offsets.data_ptr(), chars.data_ptr(), cap_chars, ws.data_ptr(), ws.numel(),
+                                        ctypes.c_void_p(stream.cuda_stream)), "pp_materialize_strings")
+    offsets._keep = (ws, vp, mp, ep)  # alive until the caller synchronises
+    return offsets, chars
 
 
 def parse_noalloc(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
@@ -391,7 +434,7 @@ def _batch_items(items):
         arr[i].out = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets),
                                _ptr(out.field_offsets), _ptr(out.column_ids),
                                ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
-                               ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result))
+                               ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result), _ptr(out.control_bitmap))
     return arr, keep
 
 

@@ -239,6 +239,7 @@ extern "C" pp_status_t pp_batch_create(const pp_dfa_t* dfas, int32_t ndfas, cons
         a.field_offsets = o.d_field_offsets;
         a.column_ids = o.d_column_ids;
         a.result = o.d_result;
+        a.ctl_out = o.d_control_bitmap;
         a.ncols = it.ncols;
         a.num_states = d.num_states;
         a.start_state = d.start_state;

@@ -1,0 +1,294 @@
+// Materialised string columns (Sec. 3.3: a column's symbol string holds its
+// fields' symbols without the control symbols). After a parse that wrote the
+// control-symbol bitmap, a string column's values -- every byte of the
+// field's span that is not a control symbol, so the enclosing quotes, the
+// first quote of a doubled pair and escape characters go -- are written back
+// to back in the Arrow large-string layout: int64 offsets[R + 1] and chars.
+//
+// Steps (all on the device, one stream, sizes read from the parse's result):
+//   1. control symbols per 256-byte block of the input, scanned: the number
+//      of control symbols before any byte is a block prefix plus at most
+//      eight bitmap words;
+//   2. per record, the value's length (span length minus its control
+//      symbols) and its number of 4 KiB pieces; both scanned: the offsets,
+//      and a piece index that spreads a long field over many wavefronts;
+//   3. one wavefront per piece: finds its record by binary search over the
+//      piece index, then copies the piece's data bytes, 64 at a time, to
+//      their place (a ballot gives each byte's rank among the data bytes).
+// A field of any length (tens of MiB) is thus copied by many wavefronts in
+// parallel.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "parparaw.h"
+
+namespace {
+
+constexpr int kBlockBytes = 256;    // bytes per control-count block (8 bitmap words)
+constexpr int64_t kPiece = 4096;    // input bytes per gather work item
+constexpr int kScanItems = 2048;    // elements per scan block (256 threads x 8)
+
+// ---- exclusive scan of int64 values -----------------------------------------
+// out[i] = sum of in[j] for j < i, i <= N; out[N] = total. N is the parse's
+// record count capped at nmax when res is set, else nmax. in and out may
+// alias (a block reads its elements before it writes them).
+
+__device__ inline int64_t count_of(int64_t nmax, const pp_result_t* res)
+{
+    if (res) {
+        const int64_t r = res->num_records;
+        return r < nmax ? r : nmax;
+    }
+    return nmax;
+}
+
+__device__ inline int64_t block_reduce(int64_t v, int64_t* sh)
+{
+    for (int d = 32; d; d >>= 1) v += __shfl_xor(v, d);
+    const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+    if (l == 0) sh[w] = v;
+    __syncthreads();
+    int64_t t = 0;
+    for (int k = 0; k < (int)(blockDim.x >> 6); ++k) t += sh[k];
+    __syncthreads();
+    return t;
+}
+
+__global__ __launch_bounds__(256) void scan_partials(const int64_t* in, int64_t nmax, const pp_result_t* res,
+                                                     int64_t* partial)
+{
+    __shared__ int64_t sh[4];
+    const int64_t N = count_of(nmax, res);
+    const int64_t base = (int64_t)blockIdx.x * kScanItems;
+    int64_t s = 0;
+    for (int k = 0; k < kScanItems / 256; ++k) {
+        const int64_t i = base + k * 256 + threadIdx.x;
+        if (i < N) s += in[i];
+    }
+    s = block_reduce(s, sh);
+    if (threadIdx.x == 0) partial[blockIdx.x] = s;
+}
+
+// one workgroup: exclusive scan of the partials (few thousand at most)
+__global__ __launch_bounds__(1024) void scan_top(int64_t* partial, int64_t nparts)
+{
+    __shared__ int64_t sh[1024];
+    int64_t carry = 0;
+    for (int64_t base = 0; base < nparts; base += 1024) {
+        const int64_t i = base + threadIdx.x;
+        const int64_t v = i < nparts ? partial[i] : 0;
+        sh[threadIdx.x] = v;
+        __syncthreads();
+        for (int d = 1; d < 1024; d <<= 1) {  // Hillis-Steele inclusive scan
+            const int64_t t = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
+            __syncthreads();
+            sh[threadIdx.x] += t;
+            __syncthreads();
+        }
+        if (i < nparts) partial[i] = carry + sh[threadIdx.x] - v;
+        carry += sh[1023];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(256) void scan_apply(const int64_t* in, int64_t* out, int64_t nmax,
+                                                  const pp_result_t* res, const int64_t* partial)
+{
+    __shared__ int64_t sh[256];
+    const int64_t N = count_of(nmax, res);
+    const int64_t base = (int64_t)blockIdx.x * kScanItems;
+    if (base > N) return;
+    // each thread owns 8 consecutive elements
+    const int64_t my = base + (int64_t)threadIdx.x * (kScanItems / 256);
+    int64_t v[kScanItems / 256];
+    int64_t sum = 0;
+    for (int k = 0; k < kScanItems / 256; ++k) {
+        v[k] = my + k < N ? in[my + k] : 0;
+        sum += v[k];
+    }
+    sh[threadIdx.x] = sum;
+    __syncthreads();
+    for (int d = 1; d < 256; d <<= 1) {
+        const int64_t t = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0;
+        __syncthreads();
+        sh[threadIdx.x] += t;
+        __syncthreads();
+    }
+    int64_t run = partial[blockIdx.x] + sh[threadIdx.x] - sum;
+    for (int k = 0; k < kScanItems / 256; ++k) {
+        const int64_t i = my + k;
+        if (i <= N) out[i] = run;  // out[N]: the total
+        run += v[k];
+    }
+}
+
+// ---- control-symbol counts ------------------------------------------------------
+
+__global__ void block_counts(const uint32_t* bitmap, int64_t nwords, int64_t nblocks, int64_t* cb)
+{
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; k < nblocks; k += stride) {
+        int64_t c = 0;
+        for (int w = 0; w < kBlockBytes / 32; ++w) {
+            const int64_t i = k * (kBlockBytes / 32) + w;
+            if (i < nwords) c += __popc(bitmap[i]);
+        }
+        cb[k] = c;
+    }
+}
+
+// control symbols before byte i (i <= n)
+__device__ inline int64_t ctl_before(const uint32_t* bitmap, const int64_t* cp, int64_t i)
+{
+    const int64_t blk = i / kBlockBytes;
+    int64_t c = cp[blk];
+    const int64_t w0 = blk * (kBlockBytes / 32), w1 = i >> 5;
+    for (int64_t w = w0; w < w1; ++w) c += __popc(bitmap[w]);
+    const uint32_t part = (uint32_t)(i & 31);
+    if (part) c += __popc(bitmap[w1] & ((1u << part) - 1u));
+    return c;
+}
+
+__global__ void value_lengths(const int64_t* begin, const int64_t* end, const uint8_t* valid, int64_t cap,
+                              const pp_result_t* res, const uint32_t* bitmap, const int64_t* cp, int64_t* len,
+                              int64_t* pieces)
+{
+    const int64_t R = count_of(cap, res);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
+        int64_t l = 0, p = 0;
+        if (valid[r]) {
+            const int64_t b = begin[r], e = end[r];
+            if (e > b) {
+                l = (e - b) - (ctl_before(bitmap, cp, e) - ctl_before(bitmap, cp, b));
+                p = (e - b + kPiece - 1) / kPiece;
+            }
+        }
+        len[r] = l;
+        pieces[r] = p;
+    }
+}
+
+// one wavefront per piece of a value
+__global__ __launch_bounds__(256) void gather_pieces(const uint8_t* in, const int64_t* begin, const int64_t* end,
+                                                     int64_t cap, const pp_result_t* res, const uint32_t* bitmap,
+                                                     const int64_t* cp, const int64_t* offsets,
+                                                     const int64_t* piece_off, uint8_t* chars, int64_t cap_chars)
+{
+    const int64_t R = count_of(cap, res);
+    const int64_t total = piece_off[R];
+    const int lane = threadIdx.x & 63;
+    const int64_t waves = (int64_t)gridDim.x * (blockDim.x >> 6);
+    for (int64_t q = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6); q < total; q += waves) {
+        // the record whose pieces hold q: the last r with piece_off[r] <= q
+        int64_t lo = 0, hi = R - 1;
+        while (lo < hi) {
+            const int64_t mid = (lo + hi + 1) >> 1;
+            if (piece_off[mid] <= q) lo = mid;
+            else hi = mid - 1;
+        }
+        const int64_t r = lo;
+        const int64_t b = begin[r], e = end[r];
+        const int64_t s0 = b + (q - piece_off[r]) * kPiece;
+        const int64_t s1 = s0 + kPiece < e ? s0 + kPiece : e;
+        int64_t out = offsets[r] + (s0 - b) - (ctl_before(bitmap, cp, s0) - ctl_before(bitmap, cp, b));
+        for (int64_t i0 = s0; i0 < s1; i0 += 64) {
+            const int64_t i = i0 + lane;
+            bool data = false;
+            uint8_t byte = 0;
+            if (i < s1) {
+                data = !((bitmap[i >> 5] >> (i & 31)) & 1u);
+                byte = in[i];
+            }
+            const uint64_t m = __ballot(data);
+            const int64_t pos = out + __popcll(m & ((1ull << lane) - 1ull));
+            if (data && pos < cap_chars) chars[pos] = byte;
+            out += __popcll(m);
+        }
+    }
+}
+
+constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
+
+struct WsLayout {
+    size_t cp, pieces, partial, total;
+};
+
+WsLayout ws_layout(int64_t n, int64_t cap_records)
+{
+    const int64_t nblocks = (n + kBlockBytes - 1) / kBlockBytes;
+    const int64_t biggest = std::max<int64_t>(nblocks, cap_records) + 1;
+    WsLayout w;
+    w.cp = 0;
+    w.pieces = align256((size_t)(nblocks + 1) * 8);
+    w.partial = w.pieces + align256((size_t)(cap_records + 1) * 8);
+    w.total = w.partial + align256((size_t)((biggest + kScanItems - 1) / kScanItems + 1) * 8);
+    return w;
+}
+
+// exclusive scan of in[0, N) into out[0, N], N <= nmax (device count via res)
+void scan(const int64_t* in, int64_t* out, int64_t nmax, const pp_result_t* res, int64_t* partial, hipStream_t s)
+{
+    const int64_t nb = nmax / kScanItems + 1;  // covers index nmax (the total)
+    hipLaunchKernelGGL(scan_partials, dim3((unsigned)nb), dim3(256), 0, s, in, nmax, res, partial);
+    hipLaunchKernelGGL(scan_top, dim3(1), dim3(1024), 0, s, partial, nb);
+    hipLaunchKernelGGL(scan_apply, dim3((unsigned)nb), dim3(256), 0, s, in, out, nmax, res, partial);
+}
+
+}  // namespace
+
+extern "C" size_t pp_materialize_workspace_size(int64_t n, int64_t cap_records)
+{
+    if (n < 0 || cap_records < 0) return 0;
+    return ws_layout(n, cap_records).total;
+}
+
+extern "C" pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed,
+                                              int32_t column, int64_t* d_offsets, uint8_t* d_chars,
+                                              int64_t cap_chars, void* d_ws, size_t ws_bytes, void* stream)
+{
+    if (n < 0 || (n > 0 && !d_in) || !parsed || !parsed->d_result || !d_offsets || cap_chars < 0 ||
+        (cap_chars > 0 && !d_chars) || !d_ws || column < 0 || column >= PP_MAX_COLUMNS)
+        return PP_ERR_ARG;
+    const int64_t cap = parsed->cap_records;
+    if (cap < 0) return PP_ERR_ARG;
+    if (n > 0 && !parsed->d_control_bitmap) return PP_ERR_ARG;  // the parse must have written it
+    if (cap > 0 && (!parsed->d_values || !parsed->d_valid || !parsed->d_str_end || !parsed->d_values[column] ||
+                    !parsed->d_valid[column] || !parsed->d_str_end[column]))
+        return PP_ERR_ARG;  // not a string column of that parse
+    const WsLayout w = ws_layout(n, cap);
+    if (ws_bytes < w.total) return PP_ERR_WORKSPACE;
+    if ((int64_t)(cap / kScanItems + 1) > ((int64_t)1 << 31)) return PP_ERR_UNSUPPORTED;
+    hipStream_t s = (hipStream_t)stream;
+    char* ws = (char*)d_ws;
+    int64_t* cp = (int64_t*)(ws + w.cp);
+    int64_t* pieces = (int64_t*)(ws + w.pieces);
+    int64_t* partial = (int64_t*)(ws + w.partial);
+    const int64_t nwords = (n + 31) / 32;
+    const int64_t nblocks = (n + kBlockBytes - 1) / kBlockBytes;
+    const uint32_t* bm = parsed->d_control_bitmap;
+    const pp_result_t* res = parsed->d_result;
+    auto grid = [](int64_t items) {
+        return dim3((unsigned)std::min<int64_t>(4096, std::max<int64_t>(1, (items + 255) / 256)));
+    };
+    if (nblocks > 0) {
+        hipLaunchKernelGGL(block_counts, grid(nblocks), dim3(256), 0, s, bm, nwords, nblocks, cp);
+        scan(cp, cp, nblocks, nullptr, partial, s);
+    }
+    if (cap > 0) {
+        const int64_t* begin = (const int64_t*)parsed->d_values[column];
+        const int64_t* end = parsed->d_str_end[column];
+        const uint8_t* valid = parsed->d_valid[column];
+        hipLaunchKernelGGL(value_lengths, grid(cap), dim3(256), 0, s, begin, end, valid, cap, res, bm, cp, d_offsets,
+                           pieces);
+        scan(d_offsets, d_offsets, cap, res, partial, s);
+        scan(pieces, pieces, cap, res, partial, s);
+        hipLaunchKernelGGL(gather_pieces, dim3(2048), dim3(256), 0, s, d_in, begin, end, cap, res, bm, cp, d_offsets,
+                           pieces, d_chars, cap_chars);
+    } else {
+        scan(d_offsets, d_offsets, 0, res, partial, s);  // offsets[0] = 0
+    }
+    return hipGetLastError() == hipSuccess ? PP_OK : PP_ERR_HIP;
+}

@@ -178,6 +178,7 @@ static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, const pp_dfa_t* df
     a.field_offsets = out->d_field_offsets;
     a.column_ids = out->d_column_ids;
     a.result = out->d_result;
+    a.ctl_out = out->d_control_bitmap;
     p.counter = (unsigned int*)d_ws;
     p.tables = (uint32_t*)((char*)d_ws + kWsHeader);
     p.colws = (ColDesc*)((char*)d_ws + kWsHeader + kWsTables);

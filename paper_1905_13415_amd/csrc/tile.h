@@ -112,6 +112,7 @@ struct TileArgs {
     int32_t invalid_state;
     uint32_t accept_mask;
     int32_t count_only;  // no outputs but the result record, whose status is then never CAPACITY
+    uint32_t* ctl_out;   // optional control-symbol bitmap of the whole input (one bit per byte)
 };
 
 
@@ -839,15 +840,24 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         const bool wave_ctl = ballot(cmask != 0) != 0;  // every lane takes part in the ballot
         if (lane == 0 && wave_ctl) s_anyctl = 1u;       // one store per wavefront
     }
-    if constexpr (B == 64) {
-        s_ctl[2 * tid] = (uint32_t)cmask;
-        s_ctl[2 * tid + 1] = (uint32_t)(cmask >> 32);
-    } else if constexpr (B == 32) {
-        s_ctl[tid] = cmask;
-    } else {  // two 16-byte chunks per bitmap word
-        const uint32_t part = cmask << ((tid & 1) * 16);
-        const uint32_t other = (uint32_t)__shfl_xor((int)part, 1);
-        if ((tid & 1) == 0) s_ctl[tid >> 1] = part | other;
+    {
+        // this chunk's words of the tile's control bitmap (and of the whole
+        // input's, when requested: words of bytes below n only)
+        uint32_t* const g = p.ctl_out ? p.ctl_out + (size_t)tile * (TILE / 32) : nullptr;
+        if constexpr (B == 64) {
+            s_ctl[2 * tid] = (uint32_t)cmask;
+            s_ctl[2 * tid + 1] = (uint32_t)(cmask >> 32);
+            if (g && c0 < tile_len) put(g, 2u * tid, (uint32_t)cmask);
+            if (g && c0 + 32 < tile_len) put(g, 2u * tid + 1u, (uint32_t)(cmask >> 32));
+        } else if constexpr (B == 32) {
+            s_ctl[tid] = cmask;
+            if (g && c0 < tile_len) put(g, (uint32_t)tid, (uint32_t)cmask);
+        } else {  // two 16-byte chunks per bitmap word
+            const uint32_t part = cmask << ((tid & 1) * 16);
+            const uint32_t other = (uint32_t)__shfl_xor((int)part, 1);
+            if ((tid & 1) == 0) s_ctl[tid >> 1] = part | other;
+            if (g && (tid & 1) == 0 && c0 < tile_len) put(g, (uint32_t)(tid >> 1), part | other);
+        }
     }
 
     // ---- 5. count scans ------------------------------------------------------------------
