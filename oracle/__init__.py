@@ -64,6 +64,8 @@ def _load():
         lib.orc_parse.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int64,
                                   ctypes.c_int64, P, P, P, P, P, P, P]
         lib.orc_conv.restype = ctypes.c_int
+        lib.orc_infer_types.restype = None
+        lib.orc_infer_types.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, P]
         lib.orc_materialize.restype = ctypes.c_int64
         lib.orc_materialize.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64, P, P, ctypes.c_int64]
         lib.orc_reject_ragged.restype = None
@@ -206,3 +208,15 @@ def materialize(buf, dfa, column: int):
     lib.orc_materialize(a.ctypes.data, len(a), ctypes.byref(d), column, R, offs.ctypes.data, chars.ctypes.data,
                         total)
     return offs, chars[:total]
+
+
+def infer_types(buf, dfa, ncols: int):
+    """Inferred column types (Sec. 4.3) of the first ncols columns and the
+    number of non-empty fields of each: (types list, nonempty int64[ncols])."""
+    lib = _load()
+    a = _as_u8(buf)
+    d = _dfa_struct(dfa)
+    types = np.zeros(max(ncols, 1), np.int32)
+    nonempty = np.zeros(max(ncols, 1), np.int64)
+    lib.orc_infer_types(a.ctypes.data, len(a), ctypes.byref(d), ncols, types.ctypes.data, nonempty.ctypes.data)
+    return [int(t) for t in types[:ncols]], nonempty[:ncols]

@@ -396,6 +396,64 @@ int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32
     return total;
 }
 
+/* Type inference (Sec. 4.3): a field's symbols (its enclosing control
+ * symbols stripped, as for conversion) admit a set of types -- INT64 if they
+ * convert as one, FLOAT64 if they follow the float grammar, DATE_DAYS and
+ * TIMESTAMP_S if they convert as those; a column's inferred type is the
+ * narrowest type every non-empty field of the column admits, in the order
+ * INT64, FLOAT64, DATE_DAYS, TIMESTAMP_S, else STRING (also for a column
+ * without non-empty fields). One sequential DFA run; columns >= ncols are
+ * ignored. nonempty[c] receives the number of non-empty fields. */
+void orc_infer_types(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t ncols, int32_t* types,
+                     int64_t* nonempty)
+{
+    enum { OK_INT = 1, OK_FLOAT = 2, OK_DATE = 4, OK_TS = 8 };
+    uint32_t* mask = (uint32_t*)malloc(sizeof(uint32_t) * (size_t)(ncols > 0 ? ncols : 1));
+    for (int32_t c = 0; c < ncols; c++) { mask[c] = OK_INT | OK_FLOAT | OK_DATE | OK_TS; nonempty[c] = 0; }
+    int32_t s = dfa->start_state;
+    int64_t col = 0, fbeg = 0;
+    int first_tag = TAG_DATA, prev_tag = TAG_DATA, last_tag = -1;
+    for (int64_t i = 0; i <= n; i++) {
+        int t, closes;
+        if (i < n) {
+            const int g = dfa->group_of[buf[i]];
+            t = dfa->tag[g][s];
+            s = dfa->next[g][s];
+            if (i == fbeg) first_tag = t;
+            closes = t == TAG_FIELD || t == TAG_RECORD;
+        } else {  /* end of input closes the last field unless a record delimiter did */
+            t = TAG_RECORD;
+            closes = n > 0 && last_tag != TAG_RECORD;
+        }
+        if (closes) {
+            if (col < ncols) {
+                int64_t b = fbeg, e = i;
+                if (e > b && first_tag == TAG_CONTROL) b++;
+                if (e - 1 >= b && prev_tag == TAG_CONTROL) e--;
+                if (e > b) {
+                    int64_t iv;
+                    uint32_t m = 0;
+                    if (conv_int64(buf + b, e - b, &iv)) m |= OK_INT;
+                    if (float_grammar(buf + b, e - b)) m |= OK_FLOAT;
+                    if (conv_date(buf + b, e - b, &iv)) m |= OK_DATE;
+                    if (conv_timestamp(buf + b, e - b, &iv)) m |= OK_TS;
+                    mask[col] &= m;
+                    nonempty[col]++;
+                }
+            }
+            col = t == TAG_RECORD ? 0 : col + 1;
+            fbeg = i + 1;
+        }
+        if (i < n) { prev_tag = t; last_tag = t; }
+    }
+    for (int32_t c = 0; c < ncols; c++) {
+        const uint32_t m = nonempty[c] ? mask[c] : 0;
+        types[c] = (m & OK_INT) ? TY_INT64 : (m & OK_FLOAT) ? TY_FLOAT64 : (m & OK_DATE) ? TY_DATE_DAYS
+                 : (m & OK_TS) ? TY_TIMESTAMP_S : TY_STRING;
+    }
+    free(mask);
+}
+
 /* Single conversions, exposed so that tests can pin them against Python's
  * int(), float() and calendar arithmetic on hand-picked cases. */
 int orc_conv(int32_t type, const uint8_t* p, int64_t len, int64_t* iv, double* dv)

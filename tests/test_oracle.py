@@ -406,6 +406,72 @@ def test_materialize_log_escapes():
     assert all(bytes(chars[offs[r]:offs[r + 1]]) == b"d t" for r in range(len(lines)))
 
 
+def test_infer_types_hand_example():
+    """Type inference (Sec. 4.3): the narrowest type every non-empty field of
+    a column admits; empty fields do not constrain; a column of empty fields
+    is a string column."""
+    t = (b'1,1.5,2020-01-01,2020-01-01 10:00:00,abc,"42",,x\n'
+         b'-3,7,2020-02-29,2020-01-01T00:00:00,12,"",,1\n')
+    types, nonempty = oracle.infer_types(t, D.csv4(), 9)
+    assert types == [D.INT64, D.FLOAT64, D.DATE_DAYS, D.TIMESTAMP_S, D.STRING, D.INT64, D.STRING, D.STRING,
+                     D.STRING]
+    assert list(nonempty) == [2, 2, 2, 2, 2, 1, 0, 2, 0]
+
+
+def _py_admits(text):
+    """The types a field admits, decided with Python's own parsers."""
+    import datetime
+    import re
+    out = set()
+    if re.fullmatch(r"[+-]?[0-9]+", text) and -2 ** 63 <= int(text) < 2 ** 63:
+        out.add(D.INT64)
+    if re.fullmatch(r"[+-]?([0-9]+(\.[0-9]*)?|\.[0-9]+)([eE][+-]?[0-9]+)?", text):
+        out.add(D.FLOAT64)
+    if re.fullmatch(r"[0-9]{4}-[0-9]{2}-[0-9]{2}", text):
+        try:
+            datetime.date(int(text[:4]), int(text[5:7]), int(text[8:10]))
+            out.add(D.DATE_DAYS)
+        except ValueError:
+            pass
+    if re.fullmatch(r"[0-9]{4}-[0-9]{2}-[0-9]{2}[ T][0-9]{2}:[0-9]{2}:[0-9]{2}", text):
+        try:
+            datetime.datetime(int(text[:4]), int(text[5:7]), int(text[8:10]), int(text[11:13]), int(text[14:16]),
+                              int(text[17:19]))
+            out.add(D.TIMESTAMP_S)
+        except ValueError:
+            pass
+    return out
+
+
+@pytest.mark.parametrize("seed", range(5))
+def test_infer_types_against_python(seed):
+    rng = random.Random(300 + seed)
+    kinds = {
+        "int": lambda: str(rng.randrange(-10 ** 6, 10 ** 6)),
+        "big": lambda: rng.choice(["9223372036854775807", "9223372036854775808", "-9223372036854775808"]),
+        "float": lambda: f"{rng.uniform(-1e4, 1e4):.{rng.randrange(0, 4)}f}",
+        "exp": lambda: f"{rng.uniform(1, 9):.2f}e{rng.randrange(-5, 5)}",
+        "date": lambda: f"{rng.randrange(1900, 2100):04d}-{rng.randrange(1, 13):02d}-{rng.randrange(1, 32):02d}",
+        "ts": lambda: f"2020-{rng.randrange(1, 13):02d}-{rng.randrange(1, 29):02d} "
+                      f"{rng.randrange(0, 25):02d}:{rng.randrange(0, 60):02d}:{rng.randrange(0, 61):02d}",
+        "word": lambda: rng.choice(["abc", "x1", "1x", "--", "1.2.3", "+", "."]),
+        "empty": lambda: "",
+    }
+    ncols = 8
+    colkinds = [[rng.choice(list(kinds)) for _ in range(rng.choice([1, 2]))] for _ in range(ncols)]
+    rows = [[kinds[rng.choice(colkinds[c])]() for c in range(ncols)] for _ in range(rng.randrange(1, 40))]
+    text = ("\n".join(",".join(r) for r in rows) + "\n").encode()
+    types, nonempty = oracle.infer_types(text, D.csv4(), ncols)
+    for c in range(ncols):
+        vals = [r[c] for r in rows if r[c] != ""]
+        admitted = {D.INT64, D.FLOAT64, D.DATE_DAYS, D.TIMESTAMP_S}
+        for v in vals:
+            admitted &= _py_admits(v)
+        want = D.STRING if not vals else next((t for t in (D.INT64, D.FLOAT64, D.DATE_DAYS, D.TIMESTAMP_S)
+                                               if t in admitted), D.STRING)
+        assert types[c] == want and nonempty[c] == len(vals), (seed, c, colkinds[c], vals[:5])
+
+
 # ---- conversions against Python's exact arithmetic -------------------------
 
 INT_CASES = ["0", "-0", "+7", "123", "-123", "9223372036854775807", "-9223372036854775808",
