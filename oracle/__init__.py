@@ -64,6 +64,8 @@ def _load():
         lib.orc_parse.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int64,
                                   ctypes.c_int64, P, P, P, P, P, P, P]
         lib.orc_conv.restype = ctypes.c_int
+        lib.orc_skip_rows.restype = ctypes.c_int64
+        lib.orc_skip_rows.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P]
         lib.orc_infer_types.restype = None
         lib.orc_infer_types.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, P]
         lib.orc_materialize.restype = ctypes.c_int64
@@ -220,3 +222,14 @@ def infer_types(buf, dfa, ncols: int):
     nonempty = np.zeros(max(ncols, 1), np.int64)
     lib.orc_infer_types(a.ctypes.data, len(a), ctypes.byref(d), ncols, types.ctypes.data, nonempty.ctypes.data)
     return [int(t) for t in types[:ncols]], nonempty[:ncols]
+
+
+def skip_rows(buf, ranges):
+    """The input without the rows (line-feed separated lines) in the
+    half-open ranges [(first, last), ...] (Sec. 4.3, skipping rows)."""
+    lib = _load()
+    a = _as_u8(buf)
+    r = np.array([x for pair in ranges for x in pair] or [0], dtype=np.int64)
+    out = np.zeros(max(len(a), 1), np.uint8)
+    m = lib.orc_skip_rows(a.ctypes.data, len(a), r.ctypes.data, len(ranges), out.ctypes.data)
+    return out[:m]

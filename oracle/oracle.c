@@ -454,6 +454,25 @@ void orc_infer_types(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t 
     free(mask);
 }
 
+/* Skipping rows (Sec. 4.3): rows are the input's line-feed separated lines
+ * (a record may span several, so this is not the DFA's record structure);
+ * row k is the bytes after the k-th line feed up to and including the next
+ * one. The bytes of every row in one of the half-open ranges [first, last)
+ * (ranges[2i], ranges[2i+1]) are dropped; the rest is copied to out in
+ * order. Returns the number of bytes kept. */
+int64_t orc_skip_rows(const uint8_t* buf, int64_t n, const int64_t* ranges, int32_t nranges, uint8_t* out)
+{
+    int64_t row = 0, m = 0;
+    for (int64_t i = 0; i < n; i++) {
+        int skip = 0;
+        for (int32_t k = 0; k < nranges; k++)
+            if (row >= ranges[2 * k] && row < ranges[2 * k + 1]) skip = 1;
+        if (!skip) out[m++] = buf[i];
+        if (buf[i] == '\n') row++;
+    }
+    return m;
+}
+
 /* Single conversions, exposed so that tests can pin them against Python's
  * int(), float() and calendar arithmetic on hand-picked cases. */
 int orc_conv(int32_t type, const uint8_t* p, int64_t len, int64_t* iv, double* dv)

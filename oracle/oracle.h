@@ -47,6 +47,8 @@ int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32
 void orc_infer_types(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t ncols, int32_t* types,
                      int64_t* nonempty);
 
+int64_t orc_skip_rows(const uint8_t* buf, int64_t n, const int64_t* ranges, int32_t nranges, uint8_t* out);
+
 int orc_conv(int32_t type, const uint8_t* p, int64_t len, int64_t* iv, double* dv);
 
 #endif

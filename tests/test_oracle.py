@@ -472,6 +472,26 @@ def test_infer_types_against_python(seed):
         assert types[c] == want and nonempty[c] == len(vals), (seed, c, colkinds[c], vals[:5])
 
 
+@pytest.mark.parametrize("seed", range(4))
+def test_skip_rows_against_splitlines(seed):
+    """Skipping rows (Sec. 4.3): the same as dropping the listed lines of
+    Python's line split (line feeds kept), quotes notwithstanding."""
+    rng = random.Random(400 + seed)
+    lines = [rng.choice(["a,b", '"x', 'y"', "", "1,2,3", '""']) for _ in range(rng.randrange(0, 50))]
+    text = "\n".join(lines) + ("\n" if seed % 2 else "")
+    rows = text.encode().split(b"\n")
+    rows = [r + b"\n" for r in rows[:-1]] + ([rows[-1]] if rows[-1] else [])
+    ranges, k = [], 0
+    while k < len(rows) + 3:
+        a = k + rng.randrange(0, 4)
+        b = a + rng.randrange(1, 4)
+        ranges.append((a, b))
+        k = b + 1
+    want = b"".join(r for i, r in enumerate(rows) if not any(a <= i < b for a, b in ranges))
+    assert bytes(oracle.skip_rows(text.encode(), ranges)) == want
+    assert bytes(oracle.skip_rows(text.encode(), [])) == text.encode()
+
+
 # ---- conversions against Python's exact arithmetic -------------------------
 
 INT_CASES = ["0", "-0", "+7", "123", "-123", "9223372036854775807", "-9223372036854775808",
