@@ -230,6 +230,50 @@ pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outp
                                    int64_t* d_offsets, uint8_t* d_chars, int64_t cap_chars, void* d_ws,
                                    size_t ws_bytes, void* stream);
 
+/*
+ * Type inference (Sec. 4.3). After pp_parse of d_in[0..n) with `parsed` as
+ * its outputs, whose first ncols columns are STRING (e.g. the schema-less
+ * parse of as many string columns as pp_infer_columns reports), ordered
+ * before this call: for each of those columns, the narrowest type that every
+ * non-empty field (enclosing control symbols stripped) admits, in the order
+ * INT64 (converts without overflow), FLOAT64 (the float grammar), DATE_DAYS,
+ * TIMESTAMP_S (valid calendar values), else STRING; a column without
+ * non-empty fields is STRING. d_types[ncols] (int32) and d_nonempty[ncols]
+ * (int64, non-empty fields per column) are device arrays; d_ws holds
+ * pp_infer_types_workspace_size(ncols) bytes. Asynchronous; no allocation.
+ */
+size_t pp_infer_types_workspace_size(int32_t ncols);
+pp_status_t pp_infer_types(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed, int32_t ncols,
+                           int32_t* d_types, int64_t* d_nonempty, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Skipping rows (Sec. 4.3): rows are the input's line-feed separated lines
+ * (row k: the bytes after the k-th line feed up to and including the next;
+ * a quoted record may span several rows), so they are dropped before the
+ * parse, by a parallel stream compaction. The bytes of every row in one of
+ * the nranges half-open ranges [ranges[2i], ranges[2i+1]) (host array,
+ * sorted, disjoint, non-empty, at most PP_MAX_SKIP_RANGES) are removed;
+ * the rest of d_in[0..n) is written to d_out (n bytes of room) in order and
+ * its length to *d_out_len (device). d_ws: pp_skip_rows_workspace_size(n)
+ * bytes. Asynchronous; no allocation. The ranges are copied during the call.
+ */
+#define PP_MAX_SKIP_RANGES 64
+size_t pp_skip_rows_workspace_size(int64_t n);
+pp_status_t pp_skip_rows(const uint8_t* d_in, int64_t n, const int64_t* ranges, int32_t nranges, uint8_t* d_out,
+                         int64_t* d_out_len, void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * Skipping records (Sec. 4.3), after pp_parse with `parsed` as outputs and
+ * `types` its schema (ncols entries), ordered before this call: the typed
+ * values of every record in the nranges half-open ranges of record indices
+ * (host array as for pp_skip_rows) get the column defaults (value 0, valid
+ * 0, empty span), so consumers read them as ignored; their fields stay in the
+ * offsets and column ids, and the counters of the result are unchanged.
+ * Asynchronous; no allocation. (Selecting columns is the PP_SKIP type.)
+ */
+pp_status_t pp_skip_records(const pp_outputs_t* parsed, int32_t ncols, const int32_t* types, const int64_t* ranges,
+                            int32_t nranges, void* stream);
+
 /* Static text for a pp_status_t. */
 const char* pp_status_str(pp_status_t s);
 

@@ -233,3 +233,19 @@ def skip_rows(buf, ranges):
     out = np.zeros(max(len(a), 1), np.uint8)
     m = lib.orc_skip_rows(a.ctypes.data, len(a), r.ctypes.data, len(ranges), out.ctypes.data)
     return out[:m]
+
+
+def skip_records(res: ParseResult, types, ranges) -> ParseResult:
+    """Skipping records (Sec. 4.3): the typed values of the records in the
+    half-open ranges [(first, last), ...] become the column defaults (value
+    0, valid 0, empty span); everything else is unchanged. Modifies and
+    returns ``res``."""
+    for c, ty in enumerate(types):
+        if ty == SKIP:
+            continue
+        for a, b in ranges:
+            res.values[c][a:b] = 0
+            res.valid[c][a:b] = 0
+            if ty == STRING:
+                res.str_end[c][a:b] = 0
+    return res

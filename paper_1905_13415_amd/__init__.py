@@ -18,7 +18,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip",
-                                                     "stream.hip", "materialize.hip")]
+                                                     "stream.hip", "materialize.hip", "infer.hip",
+                                                     "rows.hip")]
 BUILD_DIR = os.path.join(_ROOT, "_build")
 
 PP_OK = 0
@@ -107,6 +108,16 @@ def lib():
         L.pp_workspace_size.argtypes = [ctypes.c_int64, P]
         L.pp_parse.restype = ctypes.c_int32
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_skip_records.restype = ctypes.c_int32
+        L.pp_skip_records.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P]
+        L.pp_skip_rows_workspace_size.restype = ctypes.c_size_t
+        L.pp_skip_rows_workspace_size.argtypes = [ctypes.c_int64]
+        L.pp_skip_rows.restype = ctypes.c_int32
+        L.pp_skip_rows.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
+        L.pp_infer_types_workspace_size.restype = ctypes.c_size_t
+        L.pp_infer_types_workspace_size.argtypes = [ctypes.c_int32]
+        L.pp_infer_types.restype = ctypes.c_int32
+        L.pp_infer_types.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, P, P, ctypes.c_size_t, P]
         L.pp_materialize_workspace_size.restype = ctypes.c_size_t
         L.pp_materialize_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64]
         L.pp_materialize_strings.restype = ctypes.c_int32
@@ -385,6 +396,80 @@ def materialize(d_in, out: Outputs, column: int, cap_chars: Optional[int] = None
                                         ctypes.c_void_p(stream.cuda_stream)), "pp_materialize_strings")
     offsets._keep = (ws, vp, mp, ep)  # alive until the caller synchronises
     return offsets, chars
+
+
+def _outputs_struct(out: Outputs):
+    nc = len(out.types)
+    vp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.values])
+    mp = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.valid])
+    ep = (ctypes.c_void_p * max(nc, 1))(*[_ptr(x) for x in out.str_end])
+    po = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets), _ptr(out.field_offsets),
+                   _ptr(out.column_ids), ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
+                   ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result), _ptr(out.control_bitmap))
+    return po, (vp, mp, ep)
+
+
+def infer_types(d_in, out: Outputs, ncols: Optional[int] = None, stream=None):
+    """pp_infer_types over the string columns of a parse of ``d_in`` into
+    ``out``: (inferred type per column, non-empty fields per column).
+    Synchronises ``stream``."""
+    import torch
+    n = int(d_in.numel())
+    ncols = len(out.types) if ncols is None else ncols
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    types = torch.empty(max(ncols, 1), dtype=torch.int32, device=d_in.device)
+    nonempty = torch.empty(max(ncols, 1), dtype=torch.int64, device=d_in.device)
+    ws = torch.empty(max(int(lib().pp_infer_types_workspace_size(ncols)), 1), dtype=torch.uint8, device=d_in.device)
+    po, keep = _outputs_struct(out)
+    _check(lib().pp_infer_types(d_in.data_ptr() if n else None, n, ctypes.byref(po), ncols, types.data_ptr(),
+                                nonempty.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.c_void_p(stream.cuda_stream)),
+           "pp_infer_types")
+    stream.synchronize()
+    return types[:ncols].cpu().tolist(), nonempty[:ncols].cpu().numpy()
+
+
+def parse_inferred(d_in, dfa, opts: Optional[PpOptions] = None, stream=None):
+    """No schema: the column count (pp_infer_columns), a parse into that many
+    string columns, their types (pp_infer_types), then the typed parse.
+    Returns (Outputs, inferred types)."""
+    raw, inf = parse_schemaless(d_in, dfa, opts, stream)
+    types, _ = infer_types(d_in, raw, stream=stream)
+    out = parse(d_in, dfa, types, inf["num_records"], inf["num_fields"], opts=opts, stream=stream)
+    return out, types
+
+
+def skip_rows(d_in, ranges, stream=None):
+    """pp_skip_rows: the uint8 device tensor ``d_in`` without the rows
+    (line-feed separated lines) in the half-open ranges [(first, last), ...].
+    Returns a device tensor of the kept bytes (synchronises ``stream``)."""
+    import torch
+    n = int(d_in.numel())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    flat = (ctypes.c_int64 * max(2 * len(ranges), 1))(*[int(x) for pr in ranges for x in pr])
+    out = torch.empty(max(n, 1), dtype=torch.uint8, device=d_in.device)
+    out_len = torch.zeros(1, dtype=torch.int64, device=d_in.device)
+    ws = torch.empty(max(int(lib().pp_skip_rows_workspace_size(n)), 1), dtype=torch.uint8, device=d_in.device)
+    _check(lib().pp_skip_rows(d_in.data_ptr() if n else None, n, flat, len(ranges), out.data_ptr(),
+                              out_len.data_ptr(), ws.data_ptr(), ws.numel(), ctypes.c_void_p(stream.cuda_stream)),
+           "pp_skip_rows")
+    stream.synchronize()
+    return out[:int(out_len.item())]
+
+
+def skip_records(out: Outputs, ranges, stream=None) -> None:
+    """pp_skip_records: clear the typed values of the records in the
+    half-open ranges [(first, last), ...] of a parse into ``out``
+    (asynchronous on ``stream``)."""
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    flat = (ctypes.c_int64 * max(2 * len(ranges), 1))(*[int(x) for pr in ranges for x in pr])
+    po, keep = _outputs_struct(out)
+    t = (ctypes.c_int32 * max(len(out.types), 1))(*out.types)
+    _check(lib().pp_skip_records(ctypes.byref(po), len(out.types), t, flat, len(ranges),
+                                 ctypes.c_void_p(stream.cuda_stream)), "pp_skip_records")
 
 
 def parse_noalloc(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,

@@ -279,6 +279,27 @@ __device__ __noinline__ double float_slow(const Src& src, int64_t b, int64_t e)
     return __builtin_bit_cast(double, bits);
 }
 
+// [+-]?([0-9]+(\.[0-9]*)?|\.[0-9]+)([eE][+-]?[0-9]+)?: the grammar alone
+// (what conv_float64 accepts), without the conversion.
+template <class Src>
+__device__ inline bool float_grammar(const Src& src, int64_t b, int64_t e)
+{
+    int64_t i = b, nd = 0;
+    if (i < e && (src(i) == '+' || src(i) == '-')) ++i;
+    for (; i < e && is_dig(src(i)); ++i) ++nd;
+    if (i < e && src(i) == '.')
+        for (++i; i < e && is_dig(src(i)); ++i) ++nd;
+    if (nd == 0) return false;
+    if (i < e && (src(i) | 0x20u) == 'e') {
+        ++i;
+        if (i < e && (src(i) == '+' || src(i) == '-')) ++i;
+        int64_t ne = 0;
+        for (; i < e && is_dig(src(i)); ++i) ++ne;
+        if (ne == 0) return false;
+    }
+    return i == e;
+}
+
 template <class Src>
 __device__ inline bool conv_float64(const Src& src, int64_t b, int64_t e, double* out)
 {
