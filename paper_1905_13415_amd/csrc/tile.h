@@ -476,7 +476,7 @@ template <int NT, int B>
 struct TileSmem {
     static constexpr int TILE = NT * B;
     static constexpr int NW = NT / 64;
-    static constexpr int FCAP = TILE / 4;   // delimiters staged per tile
+    static constexpr int FCAP = TILE / 6;   // delimiters staged per tile
     static constexpr int RCAP = TILE / 16;  // records staged per tile
     uint32_t tnext[512];  // byte -> next state of every state
     uint32_t tcomb[512];  // byte -> per state (next*8 | tag<<6)
@@ -487,14 +487,13 @@ struct TileSmem {
     static constexpr int PRE = kLdsBefore;
     __attribute__((aligned(16))) uint8_t bytes[PRE + TILE + 32];
     uint16_t pos[FCAP];     // tile-relative delimiter positions
-    uint16_t colid[FCAP];   // column of the field each delimiter closes
+    uint8_t colid[FCAP];    // column of the field each delimiter closes (below 255; else the per-thread path)
     uint16_t recend[RCAP];  // local field index of each record delimiter
     uint32_t ctl[TILE / 32];  // control-symbol bitmap of the tile
-    ColDesc cols[PP_MAX_COLUMNS];
     double pow10[24];  // 10^k, k <= 22, for the decimal conversions
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
-    uint32_t anyctl, s0, fin, last_sa, guess;
+    uint32_t anyctl, s0, fin, last_sa, guess, colovf;
     u64 pref[4];
     u64 err, ragged, fmin, fmax;  // fmin/fmax: fewest/most fields of a record closed here
 };
@@ -532,7 +531,6 @@ __device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& s
         sm.after_delim[b] = (uint8_t)(any && same ? a : 0xffu);
         sm.ctl_any[b] = (uint8_t)ctl;
     }
-    for (int c = tid; c < p.ncols; c += NT) sm.cols[c] = p.cols[c];
 }
 
 // The whole pipeline for tile `tile` of one buffer (steps 1-7 above).
@@ -552,10 +550,10 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     uint32_t* const s_tcomb = sm.tcomb;
     uint8_t* const s_bytes = sm.bytes + TileSmem<NT, B>::PRE;  // the tile; s_bytes[-PRE, 0) precede it
     uint16_t* const s_pos = sm.pos;
-    uint16_t* const s_colid = sm.colid;
+    uint8_t* const s_colid = sm.colid;
     uint16_t* const s_recend = sm.recend;
     uint32_t* const s_ctl = sm.ctl;
-    ColDesc* const s_cols = sm.cols;
+    const ColDesc* const s_cols = p.cols;  // column descriptors in global memory
     SV<NS8>* const s_wsv = reinterpret_cast<SV<NS8>*>(&sm.wsv[0][0]);
     Cnt* const s_wcnt = sm.wcnt;
     uint32_t& s_anyctl = sm.anyctl;
@@ -576,6 +574,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     // barrier (after the ticket) precedes this; nothing written below is
     // read before the staging barrier.
     if (tid == 0) {
+        sm.colovf = 0;
         s_anyctl = 0;
         s_err = 0;
         s_ragged = 0;
@@ -932,7 +931,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 m &= m - 1;
                 const bool isr = (rm >> i) & 1u;
                 s_pos[L] = (uint16_t)(base + i);
-                s_colid[L] = (uint16_t)col;
+                s_colid[L] = (uint8_t)col;
+                if (col > 254u) sm.colovf = 1u;
                 if (isr) s_recend[lr++] = (uint16_t)L;
                 col = isr ? 0u : col + 1u;
                 ++L;
@@ -940,7 +940,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
         }
         if (vend) {
             s_pos[L] = (uint16_t)tile_len;
-            s_colid[L] = (uint16_t)col;
+            s_colid[L] = (uint8_t)col;
+            if (col > 254u) sm.colovf = 1u;
             s_recend[lr] = (uint16_t)L;
         }
     }
@@ -1006,6 +1007,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     }
     __syncthreads();
 
+    const bool staged2 = staged && sm.colovf == 0u;
     // the tile's prefixes as scalars (every lane is active here)
     const int64_t R0 = (int64_t)readlane0_64(s_pref[0]);
     const int64_t F0 = (int64_t)readlane0_64(s_pref[1]);
@@ -1043,7 +1045,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
 
     int64_t nerr = 0, nragged = 0;
     u64 fmin = ~0ull, fmax = 0;  // over the records this thread closes
-    if (staged) {
+    if (staged2) {
         {
             const int64_t roomf = p.cap_fields - F0;
             const int kf = roomf < Ft ? (int)(roomf < 0 ? 0 : roomf) : Ft;
