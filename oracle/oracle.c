@@ -364,9 +364,11 @@ void orc_reject_ragged(int32_t ncols, const int32_t* types, int64_t R, const int
  * of a record r < cap_records is appended to record r's value. offsets[r] is
  * where record r's value begins in chars, offsets[R'] (R' = min(R,
  * cap_records)) the total length; chars beyond cap_chars are not written.
- * A record without that column has an empty value. Returns the total. */
+ * A record without that column has an empty value. With terminator >= 0
+ * every value is followed by that byte (the inline-terminated form of
+ * Sec. 4.1; the offsets then include it). Returns the total. */
 int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t column, int64_t cap_records,
-                        int64_t* offsets, uint8_t* chars, int64_t cap_chars)
+                        int64_t* offsets, uint8_t* chars, int64_t cap_chars, int32_t terminator)
 {
     int32_t s = dfa->start_state;
     int64_t rec = 0, col = 0, total = 0;
@@ -378,6 +380,10 @@ int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32
         s = dfa->next[g][s];
         last_tag = t;
         if (t == TAG_RECORD) {
+            if (terminator >= 0 && rec < cap_records) {  /* inline-terminated values (Sec. 4.1) */
+                if (chars && total < cap_chars) chars[total] = (uint8_t)terminator;
+                total++;
+            }
             rec++;
             col = 0;
             if (rec <= cap_records && offsets) offsets[rec] = total;
@@ -390,6 +396,10 @@ int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32
     }
     /* end of input closes the last record unless a record delimiter did */
     if (n > 0 && last_tag != TAG_RECORD) {
+        if (terminator >= 0 && rec < cap_records) {
+            if (chars && total < cap_chars) chars[total] = (uint8_t)terminator;
+            total++;
+        }
         rec++;
         if (rec <= cap_records && offsets) offsets[rec] = total;
     }

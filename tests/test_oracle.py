@@ -368,6 +368,23 @@ def test_materialize_quoted_example():
             assert got == want, (c, dfa.name)
 
 
+def test_materialize_inline_terminated():
+    """The inline-terminated form (Sec. 4.1): every value followed by a
+    terminator byte (here the ASCII unit separator), worked by hand for the
+    quoted example; on random text, the vector-delimited values with the
+    terminator after each."""
+    data = bytes.fromhex(read_golden("quoted_example.txt")["input_hex"])
+    offs, chars = oracle.materialize(data, D.paper6(), 0, terminator=0x1F)
+    assert bytes(chars) == b'a\x1fd"e\x1f' and list(offs) == [0, 2, 6]
+    offs, chars = oracle.materialize(data, D.paper6(), 1, terminator=0x1F)
+    assert bytes(chars) == b"b,c\x1ff\x1f" and list(offs) == [0, 4, 6]
+    text = bytes(datagen.c1().data[:30000])
+    o, c = oracle.materialize(text, D.csv4(), 6)
+    ot, ct = oracle.materialize(text, D.csv4(), 6, terminator=0x1E)
+    assert bytes(ct) == b"".join(bytes(c[o[r]:o[r + 1]]) + b"\x1e" for r in range(len(o) - 1))
+    assert list(ot) == [x + i for i, x in enumerate(o)]
+
+
 @pytest.mark.parametrize("seed", range(4))
 def test_materialize_against_csv_module(seed):
     """Materialised values of every column equal Python's csv module's
