@@ -220,6 +220,9 @@ pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa
  * length, R' = min(num_records, cap_records) (d_offsets holds cap_records + 1
  * entries). A record without the column, or rejected, has an empty value.
  * Bytes beyond cap_chars are not written (compare d_offsets[R'] with it).
+ * terminator: -1 for the values alone (the offsets delimit them, the
+ * vector-delimited form of Sec. 4.1), or a byte 0..255 written after every
+ * value (the inline-terminated form; the offsets then include it).
  * Fields of any length are split over many wavefronts. d_ws: device scratch
  * of pp_materialize_workspace_size(n, cap_records) bytes. Asynchronous on
  * stream; no allocation. PP_ERR_ARG if the bitmap or the column's span
@@ -227,8 +230,8 @@ pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa
  */
 size_t pp_materialize_workspace_size(int64_t n, int64_t cap_records);
 pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed, int32_t column,
-                                   int64_t* d_offsets, uint8_t* d_chars, int64_t cap_chars, void* d_ws,
-                                   size_t ws_bytes, void* stream);
+                                   int32_t terminator, int64_t* d_offsets, uint8_t* d_chars, int64_t cap_chars,
+                                   void* d_ws, size_t ws_bytes, void* stream);
 
 /*
  * Type inference (Sec. 4.3). After pp_parse of d_in[0..n) with `parsed` as

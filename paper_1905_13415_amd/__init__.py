@@ -121,8 +121,8 @@ def lib():
         L.pp_materialize_workspace_size.restype = ctypes.c_size_t
         L.pp_materialize_workspace_size.argtypes = [ctypes.c_int64, ctypes.c_int64]
         L.pp_materialize_strings.restype = ctypes.c_int32
-        L.pp_materialize_strings.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, P, ctypes.c_int64, P,
-                                             ctypes.c_size_t, P]
+        L.pp_materialize_strings.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32, P, P,
+                                             ctypes.c_int64, P, ctypes.c_size_t, P]
         L.pp_infer_columns.restype = ctypes.c_int32
         L.pp_infer_columns.argtypes = [P, ctypes.c_int64, P, P, P, ctypes.c_size_t, P, P]
         L.pp_parse_noalloc.restype = ctypes.c_int32
@@ -367,19 +367,22 @@ def parse_schemaless(d_in, dfa, opts: Optional[PpOptions] = None, stream=None):
     return out, inf
 
 
-def materialize(d_in, out: Outputs, column: int, cap_chars: Optional[int] = None, stream=None):
+def materialize(d_in, out: Outputs, column: int, cap_chars: Optional[int] = None, stream=None,
+                terminator: int = -1):
     """pp_materialize_strings: string column ``column`` of a parse of the
     device tensor ``d_in`` into ``out`` (parsed with control_bitmap=True)
     with every control symbol removed, as device tensors (offsets int64
     [cap_records + 1], chars uint8[cap_chars]). cap_chars defaults to the
-    input size (a value is never longer than its span). Asynchronous."""
+    input size (a value is never longer than its span), plus one byte per
+    record with a terminator (>= 0: written after every value, the
+    inline-terminated form). Asynchronous."""
     import torch
     n = int(d_in.numel())
     if out.control_bitmap is None:
         raise PpError("materialize: the parse did not write the control-symbol bitmap")
     if stream is None:
         stream = torch.cuda.current_stream()
-    cap_chars = n if cap_chars is None else int(cap_chars)
+    cap_chars = (n + (out.cap_records if terminator >= 0 else 0)) if cap_chars is None else int(cap_chars)
     offsets = torch.empty(out.cap_records + 1, dtype=torch.int64, device=d_in.device)
     chars = torch.empty(max(cap_chars, 1), dtype=torch.uint8, device=d_in.device)
     ws = torch.empty(max(int(lib().pp_materialize_workspace_size(n, out.cap_records)), 1), dtype=torch.uint8,
@@ -391,7 +394,7 @@ def materialize(d_in, out: Outputs, column: int, cap_chars: Optional[int] = None
     po = PpOutputs(out.cap_records, out.cap_fields, _ptr(out.record_offsets), _ptr(out.field_offsets),
                    _ptr(out.column_ids), ctypes.cast(vp, ctypes.c_void_p), ctypes.cast(mp, ctypes.c_void_p),
                    ctypes.cast(ep, ctypes.c_void_p), _ptr(out.result), _ptr(out.control_bitmap))
-    _check(lib().pp_materialize_strings(d_in.data_ptr() if n else None, n, ctypes.byref(po), column,
+    _check(lib().pp_materialize_strings(d_in.data_ptr() if n else None, n, ctypes.byref(po), column, terminator,
                                         offsets.data_ptr(), chars.data_ptr(), cap_chars, ws.data_ptr(), ws.numel(),
                                         ctypes.c_void_p(stream.cuda_stream)), "pp_materialize_strings")
     offsets._keep = (ws, vp, mp, ep)  # alive until the caller synchronises

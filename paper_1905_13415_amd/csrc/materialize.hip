@@ -63,7 +63,7 @@ __device__ inline int64_t ctl_before(const uint32_t* bitmap, const int64_t* cp, 
 
 __global__ void value_lengths(const int64_t* begin, const int64_t* end, const uint8_t* valid, int64_t cap,
                               const pp_result_t* res, const uint32_t* bitmap, const int64_t* cp, int64_t* len,
-                              int64_t* pieces)
+                              int64_t* pieces, int64_t extra)
 {
     const int64_t R = count_of(cap, res);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -76,7 +76,7 @@ __global__ void value_lengths(const int64_t* begin, const int64_t* end, const ui
                 p = (e - b + kPiece - 1) / kPiece;
             }
         }
-        len[r] = l;
+        len[r] = l + extra;  // extra: the terminator byte of the inline-terminated form
         pieces[r] = p;
     }
 }
@@ -120,6 +120,18 @@ __global__ __launch_bounds__(256) void gather_pieces(const uint8_t* in, const in
     }
 }
 
+// the inline-terminated form: the terminator after every value
+__global__ void terminate_values(const int64_t* offsets, int64_t cap, const pp_result_t* res, uint8_t* chars,
+                                 int64_t cap_chars, uint8_t term)
+{
+    const int64_t R = count_of(cap, res);
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
+        const int64_t at = offsets[r + 1] - 1;
+        if (at < cap_chars) chars[at] = term;
+    }
+}
+
 constexpr size_t align256(size_t x) { return (x + 255) / 256 * 256; }
 
 struct WsLayout {
@@ -147,9 +159,11 @@ extern "C" size_t pp_materialize_workspace_size(int64_t n, int64_t cap_records)
 }
 
 extern "C" pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed,
-                                              int32_t column, int64_t* d_offsets, uint8_t* d_chars,
-                                              int64_t cap_chars, void* d_ws, size_t ws_bytes, void* stream)
+                                              int32_t column, int32_t terminator, int64_t* d_offsets,
+                                              uint8_t* d_chars, int64_t cap_chars, void* d_ws, size_t ws_bytes,
+                                              void* stream)
 {
+    if (terminator < -1 || terminator > 255) return PP_ERR_ARG;
     if (n < 0 || (n > 0 && !d_in) || !parsed || !parsed->d_result || !d_offsets || cap_chars < 0 ||
         (cap_chars > 0 && !d_chars) || !d_ws || column < 0 || column >= PP_MAX_COLUMNS)
         return PP_ERR_ARG;
@@ -183,11 +197,14 @@ extern "C" pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, co
         const int64_t* end = parsed->d_str_end[column];
         const uint8_t* valid = parsed->d_valid[column];
         hipLaunchKernelGGL(value_lengths, grid(cap), dim3(256), 0, s, begin, end, valid, cap, res, bm, cp, d_offsets,
-                           pieces);
+                           pieces, (int64_t)(terminator >= 0));
         scan_i64(d_offsets, d_offsets, cap, res, partial, s);
         scan_i64(pieces, pieces, cap, res, partial, s);
         hipLaunchKernelGGL(gather_pieces, dim3(2048), dim3(256), 0, s, d_in, begin, end, cap, res, bm, cp, d_offsets,
                            pieces, d_chars, cap_chars);
+        if (terminator >= 0)
+            hipLaunchKernelGGL(terminate_values, grid(cap), dim3(256), 0, s, d_offsets, cap, res, d_chars, cap_chars,
+                               (uint8_t)terminator);
     } else {
         scan_i64(d_offsets, d_offsets, 0, res, partial, s);  // offsets[0] = 0
     }

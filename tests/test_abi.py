@@ -158,3 +158,19 @@ def test_stream_argument_errors_without_device():
     assert L.pp_stream_create(ctypes.byref(shape), ctypes.byref(good), ctypes.byref(sch), ctypes.byref(h)) == -1
     assert not h.value
     assert L.pp_stream_parse(None, None, 0, None, None, None) == -1
+
+
+def test_materialize_argument_errors_without_device():
+    """pp_materialize_strings checks its arguments before any device work:
+    a terminator outside -1..255, a missing result record, a bad column."""
+    L = pp.lib()
+    po = pp.PpOutputs()
+    fake = ctypes.c_void_p(16)
+    offs = ctypes.c_void_p(64)
+    for term in (-2, 256):
+        assert L.pp_materialize_strings(fake, 8, ctypes.byref(po), 0, term, offs, fake, 8, fake, 1 << 20,
+                                        None) == -1
+    assert L.pp_materialize_strings(fake, 8, ctypes.byref(po), 0, -1, offs, fake, 8, fake, 1 << 20, None) == -1
+    po.d_result = fake
+    assert L.pp_materialize_strings(fake, 8, ctypes.byref(po), -1, 0, offs, fake, 8, fake, 1 << 20, None) == -1
+    assert L.pp_materialize_strings(fake, 8, ctypes.byref(po), 0, 0, offs, fake, 8, fake, 1 << 20, None) == -1

@@ -28,21 +28,21 @@ def u8(b):
     return np.frombuffer(bytes(b), dtype=np.uint8)
 
 
-def gpu_materialize(data, dfa, types, columns, opts=None, reject_ragged=False, cap_chars=None):
+def gpu_materialize(data, dfa, types, columns, opts=None, reject_ragged=False, cap_chars=None, terminator=-1):
     R, F = oracle.count(data, dfa)
     d_in = torch.from_numpy(np.ascontiguousarray(data).copy()).cuda() if len(data) else \
         torch.empty(0, dtype=torch.uint8, device="cuda")
     out = pp.parse(d_in, dfa, types, R, F, opts=opts, reject_ragged=reject_ragged, control_bitmap=True)
-    got = {c: pp.materialize(d_in, out, c, cap_chars=cap_chars) for c in columns}
+    got = {c: pp.materialize(d_in, out, c, cap_chars=cap_chars, terminator=terminator) for c in columns}
     torch.cuda.synchronize()
     return {c: (o.cpu().numpy(), ch.cpu().numpy()) for c, (o, ch) in got.items()}, out
 
 
-def check(data, dfa, types, opts=None, tag=""):
+def check(data, dfa, types, opts=None, tag="", terminator=-1):
     cols = [c for c, t in enumerate(types) if t == D.STRING]
-    got, _ = gpu_materialize(data, dfa, types, cols, opts)
+    got, _ = gpu_materialize(data, dfa, types, cols, opts, terminator=terminator)
     for c in cols:
-        offs, chars = oracle.materialize(data, dfa, c)
+        offs, chars = oracle.materialize(data, dfa, c, terminator=terminator)
         go, gc = got[c]
         np.testing.assert_array_equal(go, offs, err_msg=f"{tag} offsets {c}")
         np.testing.assert_array_equal(gc[:offs[-1]], chars, err_msg=f"{tag} chars {c}")
@@ -60,6 +60,15 @@ def test_quoted_example():
 def test_quoted_csv_every_shape(shape):
     g = datagen.c1()
     check(g.data, D.csv4(), list(D.SCHEMA_C1.types), pp.options(*shape) if shape else None, "c1")
+
+
+@pytest.mark.parametrize("term", [0x1E, 0x1F, 0])
+def test_inline_terminated(term):
+    """Every value followed by a terminator byte (Sec. 4.1), empty values and
+    records without the column included."""
+    g = datagen.c1()
+    check(g.data, D.csv4(), list(D.SCHEMA_C1.types), tag=f"terminated {term}", terminator=term)
+    check(u8(b'a,"x""y"\nb\n"z",\n'), D.csv4(), [D.STRING, D.STRING], tag="short", terminator=term)
 
 
 def test_log_escapes_and_brackets():
