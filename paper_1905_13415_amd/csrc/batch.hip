@@ -27,6 +27,7 @@
 #include <vector>
 
 #include "parparaw.h"
+#include "batch_internal.h"
 #include "dfa_check.h"
 #include "tile.h"
 
@@ -287,6 +288,12 @@ extern "C" int64_t pp_batch_num_tiles(const pp_batch_t* bt) { return bt ? bt->to
 
 extern "C" pp_status_t pp_batch_bind(pp_batch_t* bt, void* d_ws, size_t ws_bytes, void* stream)
 {
+    return pp::batch_bind_staged(bt, d_ws, ws_bytes, nullptr, 0, stream);
+}
+
+pp_status_t pp::batch_bind_staged(pp_batch_t* bt, void* d_ws, size_t ws_bytes, void* h_stage, size_t stage_bytes,
+                                  void* stream)
+{
     if (!bt || !d_ws) return PP_ERR_ARG;
     if (ws_bytes < bt->ws_size) return PP_ERR_WORKSPACE;
     char* ws = (char*)d_ws;
@@ -305,8 +312,14 @@ extern "C" pp_status_t pp_batch_bind(pp_batch_t* bt, void* d_ws, size_t ws_bytes
     if (!bt->cols.empty()) memcpy(bt->blob.data() + bt->off_cols, bt->cols.data(), bt->cols.size() * sizeof(ColDesc));
     if (!bt->tilemap.empty())
         memcpy(bt->blob.data() + bt->off_map, bt->tilemap.data(), bt->tilemap.size() * sizeof(uint32_t));
-    if (hipMemcpyAsync(d_ws, bt->blob.data(), bt->blob.size(), hipMemcpyHostToDevice, (hipStream_t)stream) !=
-        hipSuccess)
+    // from pinned staging when the caller has some (an asynchronous copy),
+    // else from the batch's own pageable copy
+    const void* src = bt->blob.data();
+    if (h_stage && stage_bytes >= bt->blob.size()) {
+        memcpy(h_stage, bt->blob.data(), bt->blob.size());
+        src = h_stage;
+    }
+    if (hipMemcpyAsync(d_ws, src, bt->blob.size(), hipMemcpyHostToDevice, (hipStream_t)stream) != hipSuccess)
         return PP_ERR_HIP;
     bt->d_ws = d_ws;
     return PP_OK;

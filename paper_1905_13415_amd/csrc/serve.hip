@@ -29,6 +29,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch_internal.h"
 #include "parparaw.h"
 #include "serve_sched.h"
 
@@ -67,6 +68,8 @@ struct pp_server {
     int device = 0;
     char* d_arena = nullptr;
     char* d_bws[kMaxComputeStreams] = {};  // batch workspace per compute stream
+    char* h_stage[kMaxComputeStreams] = {};  // pinned staging of a batch's descriptors, per compute stream
+    size_t stage_bytes = 0;
     size_t bws_bytes = 0;
     hipStream_t copy[kMaxCopyStreams] = {};
     hipStream_t comp[kMaxComputeStreams] = {};
@@ -148,7 +151,9 @@ bool pp_server::launch_batch(int s, std::vector<Request*>& reqs)
         for (size_t i = reqs.size(); i-- > take;) core->unready_front(reqs[i]);
         reqs.resize(take);
     }
-    if (pp_batch_bind(b, d_bws[s], bws_bytes, comp[s]) != PP_OK || pp_batch_launch(b, comp[s]) != PP_OK) {
+    // (stream s is idle: its previous batch, and the upload from its staging, have finished)
+    if (pp::batch_bind_staged(b, d_bws[s], bws_bytes, h_stage[s], stage_bytes, comp[s]) != PP_OK ||
+        pp_batch_launch(b, comp[s]) != PP_OK) {
         pp_batch_destroy(b);
         fail(PP_ERR_HIP);
         return false;
@@ -285,6 +290,8 @@ static void server_free(pp_server* sv)
         if (e) hipEventDestroy(e);
     if (sv->ev_base) hipEventDestroy(sv->ev_base);
     if (sv->h_results) hipHostFree(sv->h_results);
+    for (int s = 0; s < kMaxComputeStreams; ++s)
+        if (sv->h_stage[s]) hipHostFree(sv->h_stage[s]);
     if (sv->d_arena) hipFree(sv->d_arena);
     delete sv->core;
     delete sv;
@@ -338,6 +345,10 @@ extern "C" pp_status_t pp_server_create(const pp_server_config_t* cfg, const pp_
     sv->ev_copy.assign((size_t)c.max_slots, nullptr);
     for (int k = 0; k < c.max_slots && ok; ++k) ok = hipEventCreate(&sv->ev_copy[(size_t)k]) == hipSuccess;
     ok = ok && hipHostMalloc((void**)&sv->h_results, sizeof(pp_result_t) * (size_t)c.max_slots) == hipSuccess;
+    // descriptors of a batch: a few KiB per request plus 4 bytes per work item
+    sv->stage_bytes = std::min<size_t>(sv->bws_bytes, (size_t)16 << 20);
+    for (int s = 0; s < c.compute_streams && ok; ++s)
+        ok = hipHostMalloc((void**)&sv->h_stage[s], sv->stage_bytes) == hipSuccess;
     ok = ok && hipEventCreate(&sv->ev_base) == hipSuccess && hipEventRecord(sv->ev_base, sv->comp[0]) == hipSuccess &&
          hipEventSynchronize(sv->ev_base) == hipSuccess;
     if (!ok) { server_free(sv); return PP_ERR_HIP; }
