@@ -90,23 +90,32 @@ __device__ __forceinline__ int ser_int64(const Win& x, int len, int64_t* out)
 
 // [+-]?([0-9]+(\.[0-9]*)?|\.[0-9]+) with <= 19 digits and no exponent, in
 // Clinger's exact range (digit string below 2^53, at most 22 fraction
-// digits); anything else goes to the general path. The digit string is
-// accumulated in double precision: every partial value is an integer no
-// larger than the final one, so while the final value is below 2^53 each
-// step v*10+d is exact; a larger final value is caught by the range check
-// (rounding is monotonic, so it cannot land below 2^53).
+// digits); anything else goes to the general path. The digits of the first
+// 8 bytes are accumulated in 32-bit integers (exact), the rest in double
+// precision from there: every partial value is an integer no larger than
+// the final one, so while the final value is below 2^53 each step v*10+d
+// is exact; a larger final value is caught by the range check (rounding is
+// monotonic, so it cannot land below 2^53).
 // pow10: 10^k for 0 <= k <= 22 (a table the caller keeps in LDS).
 __device__ __forceinline__ int ser_float64(const Win& x, int len, double* out, const double* pow10)
 {
     const uint32_t c0 = x.at(0);
     const bool neg = c0 == '-';
     const bool sg = (c0 == '+') | (c0 == '-');
+    // the digits of bytes 0-7 in 32-bit integer arithmetic (at most 8 of
+    // them: below 10^8), the rest in double precision from that value on
+    uint32_t m32 = 0;
     double v = 0.0;
+    bool wide = false;  // the wavefront went past byte 7 (uniform)
     uint32_t dots = 0;  // bit i: byte i is a decimal point
     bool other = false;
 #pragma unroll
     for (int q = 0; q < kWin / 4; ++q) {  // a dword of the window per step
         if (!wave_any(4 * q < len)) break;
+        if (q == 2) {
+            v = (double)m32;
+            wide = true;
+        }
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
             const int i = 4 * q + j;
@@ -116,12 +125,17 @@ __device__ __forceinline__ int ser_float64(const Win& x, int len, double* out, c
             const bool isd = in & (d <= 9u);
             const bool isdot = in & (c == '.');
             other |= in & !isd & !isdot;
-            // a digit: v*10 + d; anything else: v*1 + 0 (no select of v needed)
-            const uint32_t dz = isd ? d : 0u;
-            v = __builtin_fma(v, isd ? 10.0 : 1.0, (double)dz);
+            if (q < 2) {
+                m32 = isd ? m32 * 10u + d : m32;
+            } else {
+                // a digit: v*10 + d; anything else: v*1 + 0 (no select of v needed)
+                const uint32_t dz = isd ? d : 0u;
+                v = __builtin_fma(v, isd ? 10.0 : 1.0, (double)dz);
+            }
             dots = isdot ? dots | (1u << i) : dots;
         }
     }
+    if (!wide) v = (double)m32;
     const int ndot = __popc(dots);
     const int nd = len - (int)sg - ndot;  // digits, when nothing else is in the field
     if (other || ndot > 1 || nd > 19) return -1;

@@ -146,13 +146,6 @@ __device__ inline u64 peek(u64* w)
 
 __device__ inline u64 ballot(bool x) { return __ballot(x); }
 
-__device__ inline u64 shfl_down64(u64 v, int d)
-{
-    uint32_t lo = (uint32_t)__shfl_down((int)(uint32_t)v, d);
-    uint32_t hi = (uint32_t)__shfl_down((int)(uint32_t)(v >> 32), d);
-    return ((u64)hi << 32) | lo;
-}
-
 __device__ inline u64 shfl_xor64(u64 v, int d)
 {
     uint32_t lo = (uint32_t)__shfl_xor((int)(uint32_t)v, d);
@@ -233,15 +226,6 @@ __device__ inline SV<NS8> sv_from_nib(uint32_t x)
     return v;
 }
 
-template <bool NS8>
-__device__ inline SV<NS8> shfl_down_sv(SV<NS8> v, int d)
-{
-    SV<NS8> r;
-    r.lo = (uint32_t)__shfl_down((int)v.lo, d);
-    r.hi = NS8 ? (uint32_t)__shfl_down((int)v.hi, d) : 0u;
-    return r;
-}
-
 // The even bits of x into the low half and the odd bits into the high half,
 // each in order (four swap steps of the standard bit de-interleave).
 __device__ __forceinline__ uint32_t unzip_bits(uint32_t x)
@@ -300,6 +284,27 @@ template <bool NS8>
 __device__ __forceinline__ SV<NS8> wave_prev_sv(SV<NS8> x)
 {
     return dpp_sv<0x138, 0xF, NS8>(x);
+}
+
+// Ordered reduction over the 64 lanes, higher lanes on the left (the
+// lookback's lane l holds the tile l places further back): DPP row shifts
+// towards lane 0 within each row of 16 (a lane whose source lies outside its
+// row receives the identity), then the four row totals read from lanes 0,
+// 16, 32 and 48. Every lane must be active. Returns the total (uniform).
+template <bool NS8>
+__device__ __forceinline__ SV<NS8> wave_reduce_desc_sv(SV<NS8> x)
+{
+    x = compose(dpp_sv<0x101, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x102, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x104, 0xF, NS8>(x), x);
+    x = compose(dpp_sv<0x108, 0xF, NS8>(x), x);
+    SV<NS8> r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        r[k].lo = (uint32_t)__builtin_amdgcn_readlane((int)x.lo, 16 * k);
+        r[k].hi = NS8 ? (uint32_t)__builtin_amdgcn_readlane((int)x.hi, 16 * k) : 0u;
+    }
+    return compose(compose(compose(r[3], r[2]), r[1]), r[0]);
 }
 
 // One DFA step through the combined table: state*8 -> next state*8.
@@ -365,9 +370,33 @@ __device__ inline Tot tot_combine(Tot a, Tot b)
     return r;
 }
 
-__device__ inline Tot shfl_down_tot(Tot t, int d)
+template <int CTRL>
+__device__ __forceinline__ u64 dpp64(u64 v)  // identity (0) from outside the row
 {
-    return {shfl_down64(t.rec, d), shfl_down64(t.fld, d), shfl_down64(t.col, d), shfl_down64(t.last, d)};
+    const uint32_t lo = dpp_move<CTRL, 0xF>(0u, (uint32_t)v), hi = dpp_move<CTRL, 0xF>(0u, (uint32_t)(v >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
+template <int CTRL>
+__device__ __forceinline__ Tot dpp_tot(Tot t)
+{
+    return {dpp64<CTRL>(t.rec), dpp64<CTRL>(t.fld), dpp64<CTRL>(t.col), dpp64<CTRL>(t.last)};
+}
+
+// The ordered lane reduction above for count prefixes (the all-zero Tot is
+// a left identity of tot_combine).
+__device__ __forceinline__ Tot wave_reduce_desc_tot(Tot x)
+{
+    x = tot_combine(dpp_tot<0x101>(x), x);
+    x = tot_combine(dpp_tot<0x102>(x), x);
+    x = tot_combine(dpp_tot<0x104>(x), x);
+    x = tot_combine(dpp_tot<0x108>(x), x);
+    Tot r[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+        r[k] = {readlane64(x.rec, 16 * k), readlane64(x.fld, 16 * k), readlane64(x.col, 16 * k),
+                readlane64(x.last, 16 * k)};
+    return tot_combine(tot_combine(tot_combine(r[3], r[2]), r[1]), r[0]);
 }
 
 // aggregate words: agg0 = nr:31 @31 | nf:31; agg1 = col:31 @31 | last:31 where
@@ -772,15 +801,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     if ((v >> 62) == 0) v = peek(p.words + (size_t)j * kWordsPerTile + W_STATE);
                 }
                 // ordered reduction, earlier tiles (higher lanes) on the left
-                SV<NS8> x = lane <= first ? sv_from_nib<NS8>((uint32_t)v) : sv_identity<NS8>();
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    SV<NS8> y = shfl_down_sv(x, d);
-                    if ((lane & (2 * d - 1)) == 0) x = compose(y, x);
-                }
-                SV<NS8> w;
-                w.lo = __builtin_amdgcn_readfirstlane(x.lo);
-                w.hi = __builtin_amdgcn_readfirstlane(x.hi);
+                const SV<NS8> x = lane <= first ? sv_from_nib<NS8>((uint32_t)v) : sv_identity<NS8>();
+                const SV<NS8> w = wave_reduce_desc_sv<NS8>(x);
                 acc = compose(w, acc);
                 if (first < 64) break;
             }
@@ -981,12 +1003,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 else if (incl_ok) x = {ir & kPayload, iF & kPayload, ic & kPayload, il & kPayload};
                 else x = tot_from_agg(g0, g1, (int64_t)j * TILE);
                 if (j < 0) x = {0ull, 0ull, kColAbs, 0ull};
-#pragma unroll
-                for (int d = 1; d < 64; d <<= 1) {
-                    Tot y = shfl_down_tot(x, d);
-                    if ((lane & (2 * d - 1)) == 0) x = tot_combine(y, x);
-                }
-                Tot w = {readlane0_64(x.rec), readlane0_64(x.fld), readlane0_64(x.col), readlane0_64(x.last)};
+                const Tot w = wave_reduce_desc_tot(x);
                 acc = have ? tot_combine(w, acc) : w;
                 have = true;
                 if (first < 64) break;
