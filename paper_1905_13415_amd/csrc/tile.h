@@ -756,18 +756,24 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             uint32_t il[B / 16];
 #pragma unroll
             for (int k = 0; k < B / 16; ++k) il[k] = 0u;
+            if constexpr (NS8) {
+                // the table as bytes: byte 8b + s is state s's entry for byte b
+                const uint8_t* const tb = reinterpret_cast<const uint8_t*>(s_tcomb);
+                uint32_t st = s8 >> 3;
 #pragma unroll
-            for (int i = 0; i < B; ++i) {
-                const uint32_t b = byte_at(i);
-                uint32_t x;
-                if constexpr (NS8) {
-                    const uint32_t e = s_tcomb[2 * b + (s8 >> 5)];
-                    x = __builtin_amdgcn_ubfe(e, s8 & 31u, 8);
-                } else {
-                    x = __builtin_amdgcn_ubfe(s_tcomb[b], s8, 8);
+                for (int i = 0; i < B; ++i) {
+                    const uint32_t x = tb[(byte_at(i) << 3) | st];
+                    st = (x >> 3) & 7u;
+                    il[i >> 4] |= (x >> 6) << (2 * (i & 15));
                 }
-                s8 = NS8 ? (x & 0x38u) : x;
-                il[i >> 4] |= (x >> 6) << (2 * (i & 15));
+                s8 = st << 3;
+            } else {
+#pragma unroll
+                for (int i = 0; i < B; ++i) {
+                    const uint32_t x = __builtin_amdgcn_ubfe(s_tcomb[byte_at(i)], s8, 8);
+                    s8 = x;
+                    il[i >> 4] |= (x >> 6) << (2 * (i & 15));
+                }
             }
 #pragma unroll
             for (int k = 0; k < B / 16; ++k) {
