@@ -150,10 +150,18 @@ typedef struct {
  * block_threads * bytes_per_thread bytes; bytes_per_thread is the chunk size
  * of Sec. 3.1. Supported (threads x bytes): 512x64 (the default), 256x64,
  * 512x32, 256x32, 256x16. Zero fields take the default. Any shape gives
- * identical outputs. */
+ * identical outputs.
+ * tile_order: 0 parses the tiles in input order. A value k > 0 (a
+ * diagnostic for the single-pass scans, whose lookbacks then meet
+ * predecessors in other states of completion) permutes each complete block
+ * of 64 consecutive tiles: the block's i-th workgroup takes tile
+ * ((2k+1) i + 37k) mod 64 of the block. Outputs are identical. Honoured by
+ * pp_parse, pp_parse_noalloc, pp_infer_columns and the streaming form;
+ * pp_batch_create and pp_server_create reject k != 0; k < 0 is PP_ERR_ARG. */
 typedef struct {
     int32_t bytes_per_thread;
     int32_t block_threads;
+    int32_t tile_order;
 } pp_options_t;
 
 /* Device scratch that pp_parse needs for an input of n bytes (tile counter

@@ -87,7 +87,8 @@ SCHEMA_REJECT_RAGGED = 1
 
 
 class PpOptions(ctypes.Structure):
-    _fields_ = [("bytes_per_thread", ctypes.c_int32), ("block_threads", ctypes.c_int32)]
+    _fields_ = [("bytes_per_thread", ctypes.c_int32), ("block_threads", ctypes.c_int32),
+                ("tile_order", ctypes.c_int32)]
 
 
 RESULT_FIELDS = ("status", "num_records", "num_fields", "first_invalid_offset", "final_state",
@@ -203,8 +204,10 @@ def dfa_struct(dfa) -> PpDfa:
     return d
 
 
-def options(bytes_per_thread: int = 0, block_threads: int = 0) -> PpOptions:
-    return PpOptions(bytes_per_thread, block_threads)
+def options(bytes_per_thread: int = 0, block_threads: int = 0, tile_order: int = 0) -> PpOptions:
+    """pp_options_t: launch shape (0: default) and the diagnostic tile order
+    (0: input order; k > 0 permutes each block of 64 tiles)."""
+    return PpOptions(bytes_per_thread, block_threads, tile_order)
 
 
 def workspace_size(n: int, opts: Optional[PpOptions] = None) -> int:

@@ -178,6 +178,7 @@ extern "C" pp_status_t pp_batch_create(const pp_dfa_t* dfas, int32_t ndfas, cons
     int nt = 512, b = 64;
     if (opts && opts->block_threads) nt = opts->block_threads;
     if (opts && opts->bytes_per_thread) b = opts->bytes_per_thread;
+    if (opts && opts->tile_order != 0) return PP_ERR_ARG;  // tiles of a batch go in order
     if (!((nt == 512 && b == 64) || (nt == 256 && b == 64) || (nt == 256 && b == 32) || (nt == 512 && b == 32) ||
           (nt == 256 && b == 16)))
         return PP_ERR_ARG;

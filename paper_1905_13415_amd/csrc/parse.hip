@@ -19,6 +19,7 @@ namespace pp {
 struct Params {
     TileArgs a;
     unsigned int* counter;  // tile ticket
+    uint32_t tile_order;    // 0: tiles in ticket order; else a permutation within blocks of 64
     uint32_t* tables;       // workspace copy of the byte tables (a.tables)
     ColDesc* colws;         // workspace copy of the column descriptors (a.cols)
     uint8_t group_of[256];
@@ -38,7 +39,20 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
     if (threadIdx.x == 0) s_ticket = atomicAdd(p.counter, 1u);
     tile_setup<NT, B, NS8>(p.a, sm);  // in flight together with the ticket
     __syncthreads();
-    parse_tile<NT, B, NS8, false>(p.a, s_ticket, sm);
+    uint32_t tile = s_ticket;
+    if (p.tile_order) {
+        // Diagnostic order: ticket i of a complete block of 64 tiles takes the
+        // block's tile (a i + c) mod 64, a odd (a permutation). A tile waits
+        // only on tiles of its own block and of earlier ones; once the earlier
+        // blocks are done, the at most 63 workgroups holding tickets of its
+        // block leave resident slots free for the rest of the block's tickets,
+        // so with 64 or more workgroups resident every wait ends (the host
+        // checks the compute-unit count).
+        const uint32_t base = tile & ~63u;
+        if (base + 64u <= (uint32_t)p.a.num_tiles)
+            tile = base + (((2u * p.tile_order + 1u) * (tile & 63u) + 37u * p.tile_order) & 63u);
+    }
+    parse_tile<NT, B, NS8, false>(p.a, tile, sm);
 }
 
 // Resets the workspace and the result before a parse; writes the outputs of
@@ -166,9 +180,19 @@ static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, const pp_dfa_t* df
     if (schema->ncols > 0 && !schema->types) return PP_ERR_SCHEMA;
     if (schema->flags & ~PP_SCHEMA_REJECT_RAGGED) return PP_ERR_SCHEMA;
     if (ws_bytes < pp_workspace_size(n, opts)) return PP_ERR_WORKSPACE;
+    const int32_t order = opts ? opts->tile_order : 0;
+    if (order < 0) return PP_ERR_ARG;
+    if (order > 0) {  // permuted blocks need 64 workgroups resident (one per compute unit suffices)
+        int dev = 0, cus = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            return PP_ERR_HIP;
+        if (cus < 64) return PP_ERR_UNSUPPORTED;
+    }
 
     Params p;
     memset(&p, 0, sizeof p);
+    p.tile_order = (uint32_t)order;
     TileArgs& a = p.a;
     a.in = d_in;
     a.n = n;

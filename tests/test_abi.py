@@ -174,3 +174,19 @@ def test_materialize_argument_errors_without_device():
     po.d_result = fake
     assert L.pp_materialize_strings(fake, 8, ctypes.byref(po), -1, 0, offs, fake, 8, fake, 1 << 20, None) == -1
     assert L.pp_materialize_strings(fake, 8, ctypes.byref(po), 0, 0, offs, fake, 8, fake, 1 << 20, None) == -1
+
+
+def test_options_layout_and_tile_order_errors():
+    """pp_options_t as the header declares it; a negative tile order is an
+    argument error, and the batched and serving forms take none."""
+    fields = _struct_fields(os.path.join(ROOT, "include", "parparaw.h"), "pp_options_t")
+    assert fields == [("int32_t", "bytes_per_thread"), ("int32_t", "block_threads"), ("int32_t", "tile_order")]
+    assert [f[0] for f in pp.PpOptions._fields_] == [n for _, n in fields]
+    good = pp.dfa_struct(D.csv4())
+    assert _call(good, opts=pp.options(0, 0, -1)) == -1
+    L = pp.lib()
+    bt = ctypes.c_void_p()
+    assert L.pp_batch_create(ctypes.byref(good), 1, None, 0, ctypes.byref(pp.options(0, 0, 3)), ctypes.byref(bt)) == -1
+    h = ctypes.c_void_p()
+    cfg = pp.PpServerConfig(1 << 30, 4, 2, 2, 0, pp.options(0, 0, 1))
+    assert L.pp_server_create(ctypes.byref(cfg), ctypes.byref(good), 1, ctypes.byref(h)) == -1

@@ -320,3 +320,26 @@ def test_first_field_of_tile_at_every_offset(k):
         data = (first + ",".join(rec) + "\n" + tail * 3).encode()
         assert data.find(HEAD_FIELDS[k - 1].encode(), len(first)) == TILE - d
         assert_same(u8(data), D.csv4(), HEAD_SCHEMA)
+
+
+# ---- tile order --------------------------------------------------------------------------------
+
+@pytest.mark.parametrize("shape", SHAPES, ids=SHAPE_IDS)
+def test_permuted_tile_order(shape):
+    """Tiles parsed out of input order (each complete block of 64 permuted,
+    the diagnostic tile_order option): the single-pass scans' lookbacks then
+    meet predecessors that have not started, published only their aggregate,
+    or finished. Outputs equal the oracle's under several permutations, for
+    quoted text (state vectors that differ per start state), the numeric CSV,
+    and an 8-state dialect; the inputs hold several complete blocks and an
+    incomplete last one."""
+    tile = (shape[0] * shape[1]) if shape else TILE
+    b, t = shape if shape else (0, 0)
+    c3 = datagen.c3(nbytes=200 * tile + 12345).data
+    c2 = datagen.c2(nbytes=150 * tile + 77).data
+    lg = datagen.log(29, 140 * tile + 5).data
+    for order in (1, 5, 22):
+        o = pp.options(b, t, order)
+        assert_same(c3, D.csv4(), D.SCHEMA_C3.types, opts=o)
+        assert_same(c2, D.csv4(), D.SCHEMA_C2.types, opts=o)
+        assert_same(lg, D.log6(), D.SCHEMA_LOG12.types, opts=o)
