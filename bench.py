@@ -131,7 +131,7 @@ PLAIN = {
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=30)
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--nbytes", type=int, default=0, help="input size of c2/c3 (0: the workload's own)")
     ap.add_argument("--bytes-per-thread", type=int, default=0)
@@ -261,7 +261,8 @@ def bench_plain(args):
             "bytes_per_thread": args.bytes_per_thread or 64, "block_threads": 512 if not args.bytes_per_thread else 256,
         },
         "kernel_ms": {"mean": round(ms_mean, 4), "median": round(ms_med, 4), "min": round(per[0], 4),
-                      "max": round(per[-1], 4)},
+                      "max": round(per[-1], 4), "p10": round(per[len(per) // 10], 4),
+                      "p90": round(per[min(len(per) - 1, (9 * len(per)) // 10)], 4)},
         "input_gbs": round(in_gbs, 2),
         "in_out_gbs": round(inout_gbs, 2),
         "output_bytes": outb,
@@ -278,6 +279,9 @@ def bench_plain(args):
             "traffic_source": TRAFFIC_FILES.get(args.workload) if default_size else None,
         },
     }
+    tr = line["roofline"]["traffic"]
+    # the measured bytes at this run's time: what the HBM actually moved
+    line["roofline"]["traffic_frac"] = round(tr / (ms_mean / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if tr else None
 
     if not args.no_cpu_baseline:
         import oracle
