@@ -100,6 +100,20 @@ def test_long_quoted_field_spanning_tiles():
     assert_same(u8(data), D.paper6(), [D.INT64, D.STRING, D.INT64])
 
 
+def test_one_field_of_200mb():
+    """The skewed input of the paper's evaluation: one record whose quoted
+    field is 200 MB (doubled quotes, delimiters and line feeds inside),
+    between short records, parsed into the same spans as the oracle's."""
+    rng = np.random.default_rng(7)
+    body = rng.integers(97, 123, size=200_000_000, dtype=np.uint8)
+    body[rng.integers(0, len(body), 20000)] = ord(",")
+    body[rng.integers(0, len(body), 20000)] = ord("\n")
+    txt = body.tobytes().replace(b"qz", b'q""z')
+    data = u8(b'1,"' + txt + b'",2.5\n2,"a""b",3\n3,short,4.25\n')
+    assert txt.count(b'""') > 100000
+    assert_same(data, D.csv4(), [D.INT64, D.STRING, D.FLOAT64])
+
+
 def test_long_numeric_field_spanning_tiles():
     data = b"7," + b"0" * (2 * TILE + 100) + b"42,x\n" + b"1.5," + b"9" * 30000 + b",y\n"
     assert_same(u8(data), D.csv4(), [D.FLOAT64, D.INT64, D.STRING])
