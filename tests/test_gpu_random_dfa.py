@@ -8,7 +8,8 @@ shape, and the tiles out of order) and the batched form, and every output
 is compared with the oracle's bit for bit. Inputs are drawn over the
 dialect's own symbols plus digits, signs and letters, so that delimiters,
 control symbols and conversions all occur, at sizes from one byte to many
-tiles."""
+tiles. String materialisation and type inference run under random dialects
+too."""
 import random
 
 import numpy as np
@@ -91,3 +92,31 @@ def test_random_dfas_batched():
     torch.cuda.synchronize()
     for i, ((d_in, d, types, out), ref) in enumerate(zip(items, refs)):
         compare(ref, out, out.result_dict(), types, tag=f"buffer {i} dialect {d}")
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_dfas_materialize_and_infer(seed):
+    """String columns materialised (control symbols removed, with and without
+    a terminator) and column types inferred, under random dialects whose
+    control symbols and delimiters sit anywhere."""
+    rnd = random.Random(5000 + seed)
+    for k in range(4):
+        dfa = random_dfa(rnd, f"m{seed}_{k}")
+        ncols = rnd.randint(1, 6)
+        types = [D.STRING] * ncols
+        data = random_input(rnd, dfa, rnd.choice([600, 70000, 200000]))
+        R, F = oracle.count(data, dfa)
+        d_in = torch.from_numpy(np.ascontiguousarray(data).copy()).cuda()
+        out = pp.parse(d_in, dfa, types, R, F, control_bitmap=True)
+        for c in range(ncols):
+            for term in (-1, 0x1F):
+                offs, chars = pp.materialize(d_in, out, c, terminator=term)
+                torch.cuda.synchronize()
+                want_o, want_c = oracle.materialize(data, dfa, c, terminator=term)
+                go = offs.cpu().numpy()
+                np.testing.assert_array_equal(go[:R + 1], want_o, err_msg=f"offsets {c} {term}")
+                np.testing.assert_array_equal(chars.cpu().numpy()[:want_o[-1]], want_c, err_msg=f"chars {c} {term}")
+        got_t, got_n = pp.infer_types(d_in, out)
+        want_t, want_n = oracle.infer_types(data, dfa, ncols)
+        assert got_t == want_t, (dfa.name, got_t, want_t)
+        np.testing.assert_array_equal(got_n, want_n)
