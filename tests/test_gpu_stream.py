@@ -146,3 +146,44 @@ def test_text_heavy_2gib_in_256mib_partitions():
     ref = same_as_oracle(g.data, D.csv4(), types, out, "c3")
     assert ref.num_records == g.nrecords
     assert out.stats["partitions"] == 8
+
+
+@pytest.mark.parametrize("seed", range(6))
+def test_random_dialects_in_small_partitions(seed):
+    """Random DFAs (tags of every kind anywhere) whose line feed ends a record
+    from every state, and whose record delimiters all return to the start
+    state, as the streaming form requires: partitions of a few KiB cut records, quoted-like regions and
+    escapes at arbitrary points."""
+    import random
+    from test_gpu_random_dfa import random_dfa, random_input
+    rnd = random.Random(900 + seed)
+    dfa = random_dfa(rnd, f"st{seed}")
+    dfa.invalid_state = D.NO_STATE
+    lf = dfa.group_of[ord("\n")]
+    if lf == dfa.num_groups - 1:  # the line feed fell into the catch-all group: give it a group of its own
+        dfa.group_symbols = dfa.group_symbols + [b"\n"]
+        dfa.next_state.insert(len(dfa.group_symbols) - 1, [0] * dfa.num_states)
+        dfa.tag.insert(len(dfa.group_symbols) - 1, [0] * dfa.num_states)
+        gm = bytearray(dfa.group_of)
+        for b in range(256):
+            if gm[b] >= len(dfa.group_symbols) - 1:
+                gm[b] += 1
+        gm[ord("\n")] = len(dfa.group_symbols) - 1
+        dfa.group_of = bytes(gm)
+        lf = len(dfa.group_symbols) - 1
+    for s in range(dfa.num_states):
+        dfa.next_state[lf][s] = dfa.start_state
+        dfa.tag[lf][s] = D.RECORD
+    for g in range(dfa.num_groups):  # every record delimiter restarts the DFA
+        for s in range(dfa.num_states):
+            if dfa.tag[g][s] == D.RECORD:
+                dfa.next_state[g][s] = dfa.start_state
+    types = [rnd.choice([D.INT64, D.FLOAT64, D.STRING, D.SKIP]) for _ in range(rnd.randint(1, 6))]
+    data = random_input(rnd, dfa, 300_000)
+    for pbytes in (4096, 5000, 65536):
+        print(f"[stream] random dialect {seed}, partitions of {pbytes}", flush=True)
+        # a random dialect may close a field or record at every byte: the
+        # per-partition capacities cover that worst case
+        cap = pbytes + 64 * KiB + 1
+        out = stream_parse(data, dfa, types, pbytes, cap_records=cap, cap_fields=cap)
+        same_as_oracle(data, dfa, types, out, f"seed {seed} P={pbytes}")
