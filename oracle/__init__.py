@@ -64,6 +64,8 @@ def _load():
         lib.orc_parse.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P, ctypes.c_int64,
                                   ctypes.c_int64, P, P, P, P, P, P, P]
         lib.orc_conv.restype = ctypes.c_int
+        lib.orc_parse_utf16.restype = ctypes.c_int
+        lib.orc_parse_utf16.argtypes = lib.orc_parse.argtypes
         lib.orc_skip_rows.restype = ctypes.c_int64
         lib.orc_skip_rows.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, P]
         lib.orc_infer_types.restype = None
@@ -120,31 +122,42 @@ def _as_u8(buf) -> np.ndarray:
     return np.ascontiguousarray(buf, dtype=np.uint8)
 
 
-def count(buf, dfa):
-    """(R, F) of the sequential run, without writing outputs."""
-    lib = _load()
+def _units(buf):
+    """UTF-16LE bytes (even length) as little-endian 16-bit code units."""
     a = _as_u8(buf)
+    if len(a) % 2:
+        raise ValueError("oracle: UTF-16 input of odd length")
+    return np.ascontiguousarray(a.view("<u2")).astype(np.uint16)
+
+
+def count(buf, dfa, utf16: bool = False):
+    """(R, F) of the sequential run, without writing outputs. ``utf16``: the
+    bytes are UTF-16LE text (Sec. 4.2)."""
+    lib = _load()
+    a = _units(buf) if utf16 else _as_u8(buf)
     d = _dfa_struct(dfa)
     res = _OrcResult()
-    rc = lib.orc_parse(a.ctypes.data, len(a), ctypes.byref(d), 0, None, 0, 0,
-                       None, None, None, None, None, None, ctypes.byref(res))
+    fn = lib.orc_parse_utf16 if utf16 else lib.orc_parse
+    rc = fn(a.ctypes.data, len(a), ctypes.byref(d), 0, None, 0, 0,
+            None, None, None, None, None, None, ctypes.byref(res))
     if rc != 0:
         raise ValueError("oracle: rejected arguments (a DFA that starts in its invalid state?)")
     return res.num_records, res.num_fields
 
 
 def parse(buf, dfa, schema_types, cap_records: Optional[int] = None,
-          cap_fields: Optional[int] = None, reject_ragged: bool = False) -> ParseResult:
+          cap_fields: Optional[int] = None, reject_ragged: bool = False, utf16: bool = False) -> ParseResult:
     """Sequential parse of ``buf`` under ``dfa`` into the full output set.
 
     With no capacities given, the exact sizes are counted first.
     ``reject_ragged``: records whose field count differs from the schema's
-    column count lose their typed values (Sec. 4.3)."""
+    column count lose their typed values (Sec. 4.3). ``utf16``: ``buf`` is
+    UTF-16LE text, parsed per code unit; positions stay byte offsets."""
     lib = _load()
-    a = _as_u8(buf)
+    a = _units(buf) if utf16 else _as_u8(buf)
     types = list(schema_types)
     if cap_records is None or cap_fields is None:
-        r, f = count(a, dfa)
+        r, f = count(buf if utf16 else a, dfa, utf16=utf16)
         cap_records = r if cap_records is None else cap_records
         cap_fields = f if cap_fields is None else cap_fields
     ncols = len(types)
@@ -169,9 +182,10 @@ def parse(buf, dfa, schema_types, cap_records: Optional[int] = None,
     tarr = np.array(types if types else [0], dtype=np.int32)
     d = _dfa_struct(dfa)
     res = _OrcResult()
-    rc = lib.orc_parse(a.ctypes.data, len(a), ctypes.byref(d), ncols, tarr.ctypes.data,
-                       cap_records, cap_fields, rec.ctypes.data, fld.ctypes.data, cid.ctypes.data,
-                       vptr, mptr, eptr, ctypes.byref(res))
+    fn = lib.orc_parse_utf16 if utf16 else lib.orc_parse
+    rc = fn(a.ctypes.data, len(a), ctypes.byref(d), ncols, tarr.ctypes.data,
+            cap_records, cap_fields, rec.ctypes.data, fld.ctypes.data, cid.ctypes.data,
+            vptr, mptr, eptr, ctypes.byref(res))
     if rc != 0:
         raise ValueError("oracle: rejected arguments (a DFA that starts in its invalid state?)")
     R = min(res.num_records, cap_records)

@@ -190,7 +190,22 @@ typedef struct {
     locale_t cloc;
     int64_t R, F, col, conv_errors, ragged;
     int64_t min_fields, max_fields; /* over the records closed so far */
+    /* UTF-16 input (Sec. 4.2): the symbols are 16-bit code units, u16[i]; a
+     * unit below 0x80 is the ASCII character of the same value and every
+     * other unit reads as the non-ASCII byte 0x80 (data of the catch-all
+     * group in DFAs whose structural symbols are ASCII). Positions in the
+     * outputs are byte offsets, unit_bytes per symbol. */
+    const uint16_t* u16;
+    int64_t unit_bytes;
+    uint8_t* text; /* a field's symbols as bytes, for its conversion */
+    int64_t text_cap;
 } run_t;
+
+static uint8_t sym_at(const run_t* r, const uint8_t* buf, int64_t i)
+{
+    if (!r->u16) return buf[i];
+    return r->u16[i] < 0x80 ? (uint8_t)r->u16[i] : (uint8_t)0x80;
+}
 
 static void write_default(run_t* r, int64_t rec, int64_t c)
 {
@@ -216,12 +231,22 @@ static void convert_field(run_t* r, const uint8_t* buf, int64_t b, int64_t e,
     if (end > begin && first_tag == TAG_CONTROL) begin++;
     if (end - 1 >= begin && last_tag == TAG_CONTROL) end--;
     int64_t len = end - begin;
-    const uint8_t* p = buf + begin;
+    const uint8_t* p = r->u16 ? NULL : buf + begin;
+    if (r->u16 && ty != TY_STRING && len > 0) { /* the field's symbols as bytes */
+        if (len > r->text_cap) {
+            free(r->text);
+            r->text = (uint8_t*)malloc((size_t)len);
+            r->text_cap = r->text ? len : 0;
+        }
+        if (!r->text) abort();
+        for (int64_t k = 0; k < len; k++) r->text[k] = sym_at(r, buf, begin + k);
+        p = r->text;
+    }
     int ok = 1;
     int64_t iv = 0;
     double dv = 0.0;
     if (ty == TY_STRING) {
-        iv = begin;
+        iv = begin * r->unit_bytes;
     } else if (len == 0) {
         ok = 0; /* empty: the column default, not an error (Sec. 4.3) */
     } else {
@@ -234,7 +259,7 @@ static void convert_field(run_t* r, const uint8_t* buf, int64_t b, int64_t e,
     if (!r->values || rec >= r->cap_records) return;
     if (ty == TY_FLOAT64) ((double*)r->values[c])[rec] = dv;
     else ((int64_t*)r->values[c])[rec] = iv;
-    if (ty == TY_STRING) r->str_end[c][rec] = end;
+    if (ty == TY_STRING) r->str_end[c][rec] = end * r->unit_bytes;
     r->valid[c][rec] = (uint8_t)ok;
 }
 
@@ -243,7 +268,7 @@ static void close_field(run_t* r, const uint8_t* buf, int64_t b, int64_t e,
                         int first_tag, int last_tag, int is_record)
 {
     /* field_offsets holds cap_fields + 1 entries, column_ids cap_fields */
-    if (r->field_offsets && r->F <= r->cap_fields) r->field_offsets[r->F] = b;
+    if (r->field_offsets && r->F <= r->cap_fields) r->field_offsets[r->F] = b * r->unit_bytes;
     if (r->column_ids && r->F < r->cap_fields) r->column_ids[r->F] = (int32_t)r->col;
     convert_field(r, buf, b, e, first_tag, last_tag, r->R, r->col);
     r->F++;
@@ -261,12 +286,12 @@ static void close_field(run_t* r, const uint8_t* buf, int64_t b, int64_t e,
     }
 }
 
-int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
-              int32_t ncols, const int32_t* types,
-              int64_t cap_records, int64_t cap_fields,
-              int64_t* record_offsets, int64_t* field_offsets, int32_t* column_ids,
-              void** values, uint8_t** valid, int64_t** str_end,
-              orc_result* res)
+static int parse_run(const uint8_t* buf, const uint16_t* u16, int64_t n, const orc_dfa* dfa,
+                     int32_t ncols, const int32_t* types,
+                     int64_t cap_records, int64_t cap_fields,
+                     int64_t* record_offsets, int64_t* field_offsets, int32_t* column_ids,
+                     void** values, uint8_t** valid, int64_t** str_end,
+                     orc_result* res)
 {
     if (!dfa || !res || n < 0 || ncols < 0) return -1;
     /* a run that starts in the invalid state has no transition into it to
@@ -286,6 +311,8 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
     r.valid = valid;
     r.str_end = str_end;
     r.cloc = newlocale(LC_ALL_MASK, "C", (locale_t)0);
+    r.u16 = u16;
+    r.unit_bytes = u16 ? 2 : 1;
 
     if (record_offsets && cap_records >= 0) record_offsets[0] = 0;
 
@@ -298,7 +325,7 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
     int64_t last_end = 0;      /* end + 1 of the last closed field */
 
     for (int64_t i = 0; i < n; i++) {
-        int g = dfa->group_of[buf[i]];
+        int g = dfa->group_of[sym_at(&r, buf, i)];
         int t = dfa->tag[g][s];
         int32_t s2 = dfa->next[g][s];
         if (dfa->invalid_state >= 0 && s2 == dfa->invalid_state &&
@@ -320,11 +347,11 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
         close_field(&r, buf, fbeg, n, first_tag, prev_tag, 1);
         last_end = n + 1;
     }
-    if (field_offsets && r.F <= cap_fields) field_offsets[r.F] = r.F ? last_end : 0;
+    if (field_offsets && r.F <= cap_fields) field_offsets[r.F] = r.F ? last_end * r.unit_bytes : 0;
 
     res->num_records = r.R;
     res->num_fields = r.F;
-    res->first_invalid_offset = first_inv;
+    res->first_invalid_offset = first_inv >= 0 ? first_inv * r.unit_bytes : -1;
     res->final_state = s;
     res->num_conversion_errors = r.conv_errors;
     res->num_ragged_records = r.ragged;
@@ -335,7 +362,31 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
     else if (!((dfa->accept_mask >> s) & 1u)) res->status = ORC_NON_ACCEPTING_END;
     else res->status = ORC_OK;
     freelocale(r.cloc);
+    free(r.text);
     return 0;
+}
+
+int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
+              int32_t ncols, const int32_t* types,
+              int64_t cap_records, int64_t cap_fields,
+              int64_t* record_offsets, int64_t* field_offsets, int32_t* column_ids,
+              void** values, uint8_t** valid, int64_t** str_end,
+              orc_result* res)
+{
+    return parse_run(buf, NULL, n, dfa, ncols, types, cap_records, cap_fields, record_offsets, field_offsets,
+                     column_ids, values, valid, str_end, res);
+}
+
+int orc_parse_utf16(const uint16_t* units, int64_t n_units, const orc_dfa* dfa,
+                    int32_t ncols, const int32_t* types,
+                    int64_t cap_records, int64_t cap_fields,
+                    int64_t* record_offsets, int64_t* field_offsets, int32_t* column_ids,
+                    void** values, uint8_t** valid, int64_t** str_end,
+                    orc_result* res)
+{
+    if (n_units > 0 && !units) return -1;
+    return parse_run(NULL, units, n_units, dfa, ncols, types, cap_records, cap_fields, record_offsets,
+                     field_offsets, column_ids, values, valid, str_end, res);
 }
 
 /* Rejecting the records that do not conform to the expected number of

@@ -38,6 +38,17 @@ int orc_parse(const uint8_t* buf, int64_t n, const orc_dfa* dfa,
               void** values, uint8_t** valid, int64_t** str_end,
               orc_result* res);
 
+/* The same run over UTF-16 text (Sec. 4.2): n_units 16-bit code units (host
+ * byte order); a unit below 0x80 is that ASCII symbol, any other unit reads
+ * as byte 0x80. Every output position is a byte offset (twice the unit
+ * index). */
+int orc_parse_utf16(const uint16_t* units, int64_t n_units, const orc_dfa* dfa,
+                    int32_t ncols, const int32_t* types,
+                    int64_t cap_records, int64_t cap_fields,
+                    int64_t* record_offsets, int64_t* field_offsets, int32_t* column_ids,
+                    void** values, uint8_t** valid, int64_t** str_end,
+                    orc_result* res);
+
 void orc_reject_ragged(int32_t ncols, const int32_t* types, int64_t R, const int64_t* record_offsets,
                        void** values, uint8_t** valid, int64_t** str_end);
 

@@ -5,7 +5,8 @@
  * ragged and long records, numbers, dates and times of every shape, fields
  * far longer than a line -- with every output buffer allocated to its exact
  * size (so an access one element past it is caught) and with capacities
- * below the counts. Also checks that the counting run, the full run and the
+ * below the counts, and the UTF-16 entry point on the same inputs widened to
+ * code units (with units outside ASCII and surrogates mixed in). Also checks that the counting run, the full run and the
  * capacity-limited runs agree on the counts. Prints "ok <checks>" at the end.
  */
 #include <stdint.h>
@@ -247,6 +248,45 @@ static void run(const uint8_t* buf, int64_t n, const orc_dfa* d, int64_t under)
     free(cid);
 }
 
+/* The UTF-16 entry point: the same bytes widened to code units, some of them
+ * replaced by units outside ASCII (and surrogates), with exactly sized
+ * buffers. */
+static void run_utf16(const uint8_t* buf, int64_t n, const orc_dfa* d)
+{
+    uint16_t* u = (uint16_t*)xmalloc((size_t)n * 2);
+    for (int64_t i = 0; i < n; ++i) {
+        const int64_t k = rnd_below(10);
+        u[i] = k == 0 ? (uint16_t)(0x80 + rnd_below(0xff80)) : k == 1 ? (uint16_t)(0xd800 + rnd_below(0x800)) : buf[i];
+    }
+    static const int32_t types[6] = {T_INT64, T_FLOAT64, T_STRING, T_TIMESTAMP, T_DATE, T_STRING};
+    orc_result cnt, res;
+    CHECK(orc_parse_utf16(u, n, d, 0, NULL, 0, 0, NULL, NULL, NULL, NULL, NULL, NULL, &cnt) == 0);
+    const int64_t R = cnt.num_records, F = cnt.num_fields;
+    int64_t* rec = (int64_t*)xmalloc((size_t)(R + 1) * 8);
+    int64_t* fld = (int64_t*)xmalloc((size_t)(F + 1) * 8);
+    int32_t* cid = (int32_t*)xmalloc((size_t)F * 4);
+    void* values[6];
+    uint8_t* valid[6];
+    int64_t* ends[6];
+    for (int c = 0; c < 6; ++c) {
+        values[c] = xmalloc((size_t)R * 8);
+        valid[c] = (uint8_t*)xmalloc((size_t)R);
+        ends[c] = types[c] == T_STRING ? (int64_t*)xmalloc((size_t)R * 8) : NULL;
+    }
+    CHECK(orc_parse_utf16(u, n, d, 6, types, R, F, rec, fld, cid, values, valid, ends, &res) == 0);
+    CHECK(res.num_records == R && res.num_fields == F && res.status != ORC_CAPACITY);
+    for (int64_t k = 0; k + 1 <= F; ++k) CHECK(fld[k] % 2 == 0 && fld[k] <= fld[k + 1]);
+    for (int c = 0; c < 6; ++c) {
+        free(values[c]);
+        free(valid[c]);
+        free(ends[c]);
+    }
+    free(rec);
+    free(fld);
+    free(cid);
+    free(u);
+}
+
 static void run_skip_rows(const uint8_t* buf, int64_t n)
 {
     int64_t lines = 1;
@@ -308,6 +348,7 @@ int main(void)
         for (int d = 0; d < 2; ++d) {
             run(in, b.n, &dfas[d], 0);
             run(in, b.n, &dfas[d], 1 + rnd_below(5));
+            run_utf16(in, b.n, &dfas[d]);
         }
         run_skip_rows(in, b.n);
         free(in);

@@ -719,3 +719,80 @@ def test_start_in_invalid_state_rejected():
     d.invalid_state = d.start_state
     with pytest.raises(ValueError):
         oracle.parse(b"1,2\n", d, [D.INT64])
+
+
+# ---- UTF-16 input (Sec. 4.2, multi-byte symbols) ---------------------------------
+
+def _same_doubled(r8, r16, types):
+    """The UTF-16 parse of ASCII text equals the byte parse with every
+    position doubled."""
+    assert (r16.status, r16.num_records, r16.num_fields) == (r8.status, r8.num_records, r8.num_fields)
+    assert r16.first_invalid_offset == (2 * r8.first_invalid_offset if r8.first_invalid_offset >= 0 else -1)
+    assert (r16.final_state, r16.num_conversion_errors, r16.num_ragged_records) == \
+        (r8.final_state, r8.num_conversion_errors, r8.num_ragged_records)
+    assert list(r16.record_offsets) == list(r8.record_offsets)
+    assert list(r16.field_offsets) == [2 * x for x in r8.field_offsets]
+    assert list(r16.column_ids) == list(r8.column_ids)
+    for c, ty in enumerate(types):
+        if ty == D.SKIP:
+            continue
+        if ty == D.STRING:
+            assert list(r16.values[c]) == [2 * x for x in r8.values[c]]
+            assert list(r16.str_end[c]) == [2 * x for x in r8.str_end[c]]
+        else:
+            assert r16.values[c].tobytes() == r8.values[c].tobytes()
+        assert list(r16.valid[c]) == list(r8.valid[c])
+
+
+@pytest.mark.parametrize("name", ["csv4", "paper6", "log6"])
+def test_utf16_ascii_text_is_the_byte_parse_doubled(name):
+    dfa = D.ALL_DFAS[name]()
+    rnd = random.Random(31)
+    alphabet = b"".join(dfa.group_symbols) + b"a1.-e9"
+    types = [D.STRING, D.INT64, D.FLOAT64, D.STRING, D.SKIP, D.INT64]
+    for n in (0, 1, 2, 57, 3000):
+        text = bytes(rnd.choice(alphabet) for _ in range(n))
+        r8 = oracle.parse(text, dfa, types)
+        r16 = oracle.parse(text.decode("latin-1").encode("utf-16-le"), dfa, types, utf16=True)
+        _same_doubled(r8, r16, types)
+    g = datagen.c1()
+    data = bytes(g.data[:200000])
+    _same_doubled(oracle.parse(data, D.csv4(), D.SCHEMA_C1.types),
+                  oracle.parse(data.decode("latin-1").encode("utf-16-le"), D.csv4(), D.SCHEMA_C1.types, utf16=True),
+                  D.SCHEMA_C1.types)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_utf16_against_csv_module(seed):
+    """Random RFC-4180 text with non-ASCII characters (Latin, CJK, characters
+    outside the BMP as surrogate pairs, a fullwidth comma that is data) in
+    UTF-16LE: every string field, read from its byte span and with its
+    doubled quotes undone, equals Python's csv module's field."""
+    import csv
+    import io
+    rng = random.Random(400 + seed)
+    pieces = ["", "7", "é", "漢字", "😀x", '"x,y"', '"a\nb"', '"say ""hi"""', '""', "a，b", "-1.5"]
+    recs = [",".join(rng.choice(pieces) for _ in range(rng.choice([1, 2, 3, 4, 4, 6])))
+            for _ in range(rng.randrange(5, 80))]
+    text = "\n".join(recs) + ("\n" if seed % 2 else "")
+    rows = list(csv.reader(io.StringIO(text, newline="")))
+    b16 = text.encode("utf-16-le")
+    r = oracle.parse(b16, D.csv4(), [D.STRING] * 6, utf16=True)
+    assert r.status == oracle.STATUS_OK and r.num_records == len(rows)
+    for k, row in enumerate(rows):
+        for c in range(6):
+            want = row[c] if c < len(row) else ""
+            got = b16[r.values[c][k]:r.str_end[c][k]].decode("utf-16-le")
+            quoted = r.str_end[c][k] < len(b16) and b16[r.str_end[c][k]:r.str_end[c][k] + 2] == '"'.encode("utf-16-le")
+            assert (got.replace('""', '"') if quoted else got) == want, (seed, k, c)
+
+
+def test_utf16_numbers_and_non_ascii_digits():
+    """ASCII numerals convert as in byte text; digits outside ASCII (here
+    Arabic-Indic) are not digits of the grammar: a conversion error."""
+    text = "12,2.5,2020-01-02\n٣,3.0,2020-01-0٣\n"
+    r = oracle.parse(text.encode("utf-16-le"), D.csv4(), [D.INT64, D.FLOAT64, D.DATE_DAYS], utf16=True)
+    assert r.num_records == 2 and r.num_conversion_errors == 2
+    assert list(r.values[0]) == [12, 0] and list(r.valid[0]) == [1, 0]
+    assert list(r.values[1]) == [2.5, 3.0]
+    assert list(r.valid[2]) == [1, 0] and r.values[2][0] == 18263
