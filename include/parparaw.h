@@ -156,7 +156,8 @@ typedef struct {
  * predecessors in other states of completion) permutes each complete block
  * of 64 consecutive tiles: the block's i-th workgroup takes tile
  * ((2k+1) i + 37k) mod 64 of the block. Outputs are identical. Honoured by
- * pp_parse, pp_parse_noalloc, pp_infer_columns and the streaming form;
+ * pp_parse, pp_parse_noalloc, pp_parse_utf16, pp_infer_columns and the
+ * streaming form;
  * pp_batch_create and pp_server_create reject k != 0; k < 0 is PP_ERR_ARG. */
 typedef struct {
     int32_t bytes_per_thread;
@@ -240,6 +241,26 @@ size_t pp_materialize_workspace_size(int64_t n, int64_t cap_records);
 pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed, int32_t column,
                                    int32_t terminator, int64_t* d_offsets, uint8_t* d_chars, int64_t cap_chars,
                                    void* d_ws, size_t ws_bytes, void* stream);
+
+/*
+ * UTF-16 text (Sec. 4.2, multi-byte symbols). d_in holds n_units 16-bit code
+ * units in the device's byte order (little-endian: UTF-16LE), any alignment
+ * of 2. Parsed as pp_parse parses bytes, one symbol per code unit: a unit
+ * below 0x80 is that ASCII symbol, every other unit (including surrogate
+ * halves) reads as byte 0x80, so the DFA's structural symbols are ASCII and
+ * all other characters are data of the group of 0x80. Every position in the
+ * outputs (field offsets, string spans, the first invalid offset) is a byte
+ * offset into d_in (twice the unit index); the control-symbol bitmap, when
+ * requested, has one bit per code unit. Numbers, dates and times follow the
+ * same grammars (ASCII digits). d_ws: pp_workspace_size_utf16(n_units, opts)
+ * bytes (a one-byte-per-unit copy of the input, then pp_parse's workspace).
+ * Errors as pp_parse, returned before any work is queued. Asynchronous on
+ * stream; no allocation.
+ */
+size_t pp_workspace_size_utf16(int64_t n_units, const pp_options_t* opts);
+pp_status_t pp_parse_utf16(const uint16_t* d_in, int64_t n_units, const pp_dfa_t* dfa, const pp_schema_t* schema,
+                           const pp_outputs_t* out, void* d_ws, size_t ws_bytes, const pp_options_t* opts,
+                           void* stream);
 
 /*
  * Type inference (Sec. 4.3). After pp_parse of d_in[0..n) with `parsed` as

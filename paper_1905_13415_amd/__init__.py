@@ -19,7 +19,7 @@ _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip",
                                                      "stream.hip", "materialize.hip", "infer.hip",
-                                                     "rows.hip")]
+                                                     "rows.hip", "utf16.hip")]
 BUILD_DIR = os.path.join(_ROOT, "_build")
 
 PP_OK = 0
@@ -109,6 +109,10 @@ def lib():
         L.pp_workspace_size.argtypes = [ctypes.c_int64, P]
         L.pp_parse.restype = ctypes.c_int32
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_parse_utf16.restype = ctypes.c_int32
+        L.pp_parse_utf16.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_workspace_size_utf16.restype = ctypes.c_size_t
+        L.pp_workspace_size_utf16.argtypes = [ctypes.c_int64, P]
         L.pp_skip_records.restype = ctypes.c_int32
         L.pp_skip_records.argtypes = [P, ctypes.c_int32, P, P, ctypes.c_int32, P]
         L.pp_skip_rows_workspace_size.restype = ctypes.c_size_t
@@ -339,6 +343,32 @@ def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
     call = Call(d_in, n, dfa, types, out, ws, opts, reject_ragged)
     call.launch(stream)
     out._call = call  # keep workspace alive until the caller synchronises
+    return out
+
+
+def parse_utf16(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
+                opts: Optional[PpOptions] = None, stream=None, reject_ragged: bool = False) -> Outputs:
+    """pp_parse_utf16 (Sec. 4.2): parse the UTF-16LE text in the device
+    tensor ``d_in`` (uint8 of even length, or int16/uint16 code units); every
+    position in the outputs is a byte offset into it. Asynchronous."""
+    import torch
+    if d_in.dtype == torch.uint8:
+        if d_in.numel() % 2:
+            raise PpError("parse_utf16: UTF-16 text of odd byte length")
+        n_units = int(d_in.numel()) // 2
+    else:
+        n_units = int(d_in.numel())
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device)
+    ws = torch.empty(max(int(lib().pp_workspace_size_utf16(n_units, ctypes.byref(opts) if opts else None)), 1),
+                     dtype=torch.uint8, device=d_in.device)
+    call = Call(d_in, n_units, dfa, types, out, ws, opts, reject_ragged)
+    _check(lib().pp_parse_utf16(d_in.data_ptr() if n_units else None, n_units, ctypes.byref(call.dfa),
+                                ctypes.byref(call.schema), ctypes.byref(call.outs), ws.data_ptr(), ws.numel(),
+                                ctypes.byref(opts) if opts else None, ctypes.c_void_p(stream.cuda_stream)),
+           "pp_parse_utf16")
+    out._call = call  # keep the workspace alive until the caller synchronises
     return out
 
 

@@ -190,3 +190,33 @@ def test_options_layout_and_tile_order_errors():
     h = ctypes.c_void_p()
     cfg = pp.PpServerConfig(1 << 30, 4, 2, 2, 0, pp.options(0, 0, 1))
     assert L.pp_server_create(ctypes.byref(cfg), ctypes.byref(good), 1, ctypes.byref(h)) == -1
+
+
+def test_utf16_argument_errors_without_device():
+    """pp_parse_utf16 rejects bad arguments before it queues any work."""
+    L = pp.lib()
+    good = pp.dfa_struct(D.csv4())
+    types = (ctypes.c_int32 * 1)(0)
+    sch = pp.PpSchema(1, 0, ctypes.cast(types, ctypes.c_void_p))
+    fake = ctypes.c_void_p(0x1000)
+    vals = (ctypes.c_void_p * 1)(0x2000)
+    valid = (ctypes.c_void_p * 1)(0x3000)
+    outs = pp.PpOutputs(4, 4, fake, fake, fake, ctypes.cast(vals, ctypes.c_void_p), ctypes.cast(valid, ctypes.c_void_p),
+                        None, fake, None)
+    ws = L.pp_workspace_size_utf16(16, None)
+    assert ws >= L.pp_workspace_size(16, None) + 16
+    assert L.pp_workspace_size_utf16(-1, None) == 0
+
+    def call(dfa=good, n=16, inp=fake, schema=sch, wsb=ws, opts=None):
+        return L.pp_parse_utf16(inp, n, ctypes.byref(dfa), ctypes.byref(schema), ctypes.byref(outs), fake, wsb,
+                                ctypes.byref(opts) if opts else None, None)
+    assert call(n=-1) == -1
+    assert call(inp=None) == -1
+    bad = pp.dfa_struct(D.csv4())
+    bad.start_state = 6
+    assert call(dfa=bad) == -2
+    badt = (ctypes.c_int32 * 1)(9)
+    assert call(schema=pp.PpSchema(1, 0, ctypes.cast(badt, ctypes.c_void_p))) == -3
+    assert call(wsb=ws - 1) == -4
+    assert call(opts=pp.options(48, 256)) == -1
+    assert call(opts=pp.options(0, 0, -2)) == -1
