@@ -73,6 +73,8 @@ def _load():
         lib.orc_materialize.restype = ctypes.c_int64
         lib.orc_materialize.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int64, P, P, ctypes.c_int64,
                                         ctypes.c_int32]
+        lib.orc_materialize_utf16.restype = ctypes.c_int64
+        lib.orc_materialize_utf16.argtypes = lib.orc_materialize.argtypes
         lib.orc_reject_ragged.restype = None
         lib.orc_reject_ragged.argtypes = [ctypes.c_int32, P, ctypes.c_int64, P, P, P, P]
         lib.orc_conv.argtypes = [ctypes.c_int32, P, ctypes.c_int64,
@@ -211,21 +213,21 @@ def convert(type_code: int, text: bytes):
     return bool(ok), iv.value, dv.value
 
 
-def materialize(buf, dfa, column: int, terminator: int = -1):
+def materialize(buf, dfa, column: int, terminator: int = -1, utf16: bool = False):
     """A string column's materialised values (all control symbols removed),
     as (offsets int64[R+1], chars uint8[total]) in the Arrow large-string
     layout; terminator >= 0 appends that byte to every value (the
-    inline-terminated form)."""
+    inline-terminated form). ``utf16``: UTF-16LE text; offsets count code
+    units and chars are uint16 code units."""
     lib = _load()
-    a = _as_u8(buf)
-    R, _ = count(a, dfa)
+    a = _units(buf) if utf16 else _as_u8(buf)
+    R, _ = count(buf if utf16 else a, dfa, utf16=utf16)
     d = _dfa_struct(dfa)
     offs = np.zeros(R + 1, np.int64)
-    total = lib.orc_materialize(a.ctypes.data, len(a), ctypes.byref(d), column, R, offs.ctypes.data, None, 0,
-                                terminator)
-    chars = np.zeros(max(total, 1), np.uint8)
-    lib.orc_materialize(a.ctypes.data, len(a), ctypes.byref(d), column, R, offs.ctypes.data, chars.ctypes.data,
-                        total, terminator)
+    fn = lib.orc_materialize_utf16 if utf16 else lib.orc_materialize
+    total = fn(a.ctypes.data, len(a), ctypes.byref(d), column, R, offs.ctypes.data, None, 0, terminator)
+    chars = np.zeros(max(total, 1), np.uint16 if utf16 else np.uint8)
+    fn(a.ctypes.data, len(a), ctypes.byref(d), column, R, offs.ctypes.data, chars.ctypes.data, total, terminator)
     return offs, chars[:total]
 
 

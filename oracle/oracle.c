@@ -457,6 +457,49 @@ int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32
     return total;
 }
 
+/* The same over UTF-16 text (Sec. 4.2): symbols are code units (a unit below
+ * 0x80 is that ASCII symbol, any other reads as byte 0x80), the values'
+ * data units are copied as they are, offsets count code units, and the
+ * terminator is a code unit. */
+int64_t orc_materialize_utf16(const uint16_t* units, int64_t n, const orc_dfa* dfa, int32_t column,
+                              int64_t cap_records, int64_t* offsets, uint16_t* chars, int64_t cap_chars,
+                              int32_t terminator)
+{
+    int32_t s = dfa->start_state;
+    int64_t rec = 0, col = 0, total = 0;
+    int last_tag = -1;
+    if (cap_records >= 0 && offsets) offsets[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const int g = dfa->group_of[units[i] < 0x80 ? units[i] : 0x80];
+        const int t = dfa->tag[g][s];
+        s = dfa->next[g][s];
+        last_tag = t;
+        if (t == TAG_RECORD) {
+            if (terminator >= 0 && rec < cap_records) {
+                if (chars && total < cap_chars) chars[total] = (uint16_t)terminator;
+                total++;
+            }
+            rec++;
+            col = 0;
+            if (rec <= cap_records && offsets) offsets[rec] = total;
+        } else if (t == TAG_FIELD) {
+            col++;
+        } else if (t == TAG_DATA && col == column && rec < cap_records) {
+            if (chars && total < cap_chars) chars[total] = units[i];
+            total++;
+        }
+    }
+    if (n > 0 && last_tag != TAG_RECORD) {
+        if (terminator >= 0 && rec < cap_records) {
+            if (chars && total < cap_chars) chars[total] = (uint16_t)terminator;
+            total++;
+        }
+        rec++;
+        if (rec <= cap_records && offsets) offsets[rec] = total;
+    }
+    return total;
+}
+
 /* Type inference (Sec. 4.3): a field's symbols (its enclosing control
  * symbols stripped, as for conversion) admit a set of types -- INT64 if they
  * convert as one, FLOAT64 if they follow the float grammar, DATE_DAYS and

@@ -55,6 +55,10 @@ void orc_reject_ragged(int32_t ncols, const int32_t* types, int64_t R, const int
 int64_t orc_materialize(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t column, int64_t cap_records,
                         int64_t* offsets, uint8_t* chars, int64_t cap_chars, int32_t terminator);
 
+int64_t orc_materialize_utf16(const uint16_t* units, int64_t n, const orc_dfa* dfa, int32_t column,
+                              int64_t cap_records, int64_t* offsets, uint16_t* chars, int64_t cap_chars,
+                              int32_t terminator);
+
 void orc_infer_types(const uint8_t* buf, int64_t n, const orc_dfa* dfa, int32_t ncols, int32_t* types,
                      int64_t* nonempty);
 

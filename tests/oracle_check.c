@@ -276,6 +276,15 @@ static void run_utf16(const uint8_t* buf, int64_t n, const orc_dfa* d)
     CHECK(orc_parse_utf16(u, n, d, 6, types, R, F, rec, fld, cid, values, valid, ends, &res) == 0);
     CHECK(res.num_records == R && res.num_fields == F && res.status != ORC_CAPACITY);
     for (int64_t k = 0; k + 1 <= F; ++k) CHECK(fld[k] % 2 == 0 && fld[k] <= fld[k + 1]);
+    for (int32_t term = -1; term <= 0x2028; term += 0x2029) {
+        int64_t* offs = (int64_t*)xmalloc((size_t)(R + 1) * 8);
+        const int64_t total = orc_materialize_utf16(u, n, d, 2, R, offs, NULL, 0, term);
+        CHECK(total >= 0 && offs[R] == total);
+        uint16_t* chars = (uint16_t*)xmalloc((size_t)total * 2);
+        CHECK(orc_materialize_utf16(u, n, d, 2, R, offs, chars, total, term) == total);
+        free(chars);
+        free(offs);
+    }
     for (int c = 0; c < 6; ++c) {
         free(values[c]);
         free(valid[c]);

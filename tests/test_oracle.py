@@ -796,3 +796,28 @@ def test_utf16_numbers_and_non_ascii_digits():
     assert list(r.values[0]) == [12, 0] and list(r.valid[0]) == [1, 0]
     assert list(r.values[1]) == [2.5, 3.0]
     assert list(r.valid[2]) == [1, 0] and r.values[2][0] == 18263
+
+
+@pytest.mark.parametrize("seed", range(3))
+def test_utf16_materialize_against_csv_module(seed):
+    """Materialised UTF-16 values (control symbols removed, code units kept)
+    equal Python's csv module's fields on text with non-ASCII characters;
+    with a terminator, every value is followed by that code unit."""
+    import csv
+    import io
+    rng = random.Random(600 + seed)
+    pieces = ["", "7", "é", "漢字", "😀x", '"x,y"', '"a\nb"', '"say ""hi"""', '""', '""""', "a，b"]
+    recs = [",".join(rng.choice(pieces) for _ in range(rng.choice([1, 2, 3, 4, 4, 6])))
+            for _ in range(rng.randrange(5, 80))]
+    text = "\n".join(recs) + ("\n" if seed % 2 else "")
+    rows = list(csv.reader(io.StringIO(text, newline="")))
+    b16 = text.encode("utf-16-le")
+    for c in range(6):
+        offs, chars = oracle.materialize(b16, D.csv4(), c, utf16=True)
+        assert len(offs) == len(rows) + 1
+        for r, row in enumerate(rows):
+            want = row[c] if c < len(row) else ""
+            assert chars[offs[r]:offs[r + 1]].tobytes().decode("utf-16-le") == want, (seed, c, r)
+        toffs, tchars = oracle.materialize(b16, D.csv4(), c, terminator=0x2028, utf16=True)
+        assert list(toffs) == [o + k for k, o in enumerate(offs)]
+        assert all(tchars[toffs[r + 1] - 1] == 0x2028 for r in range(len(rows)))
