@@ -258,6 +258,15 @@ pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outp
  * stream; no allocation.
  */
 size_t pp_workspace_size_utf16(int64_t n_units, const pp_options_t* opts);
+/* Materialised string column of a pp_parse_utf16 parse (which wrote the
+ * control-symbol bitmap, one bit per code unit): as pp_materialize_strings,
+ * with code units for bytes -- d_chars receives the values' data code units
+ * (cap_chars of them), d_offsets counts code units, the terminator is -1 or
+ * a code unit 0..0xffff, and the workspace is
+ * pp_materialize_workspace_size(n_units, cap_records). */
+pp_status_t pp_materialize_strings_utf16(const uint16_t* d_in, int64_t n_units, const pp_outputs_t* parsed,
+                                         int32_t column, int32_t terminator, int64_t* d_offsets, uint16_t* d_chars,
+                                         int64_t cap_chars, void* d_ws, size_t ws_bytes, void* stream);
 pp_status_t pp_parse_utf16(const uint16_t* d_in, int64_t n_units, const pp_dfa_t* dfa, const pp_schema_t* schema,
                            const pp_outputs_t* out, void* d_ws, size_t ws_bytes, const pp_options_t* opts,
                            void* stream);

@@ -111,6 +111,9 @@ def lib():
         L.pp_parse.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
         L.pp_parse_utf16.restype = ctypes.c_int32
         L.pp_parse_utf16.argtypes = [P, ctypes.c_int64, P, P, P, P, ctypes.c_size_t, P, P]
+        L.pp_materialize_strings_utf16.restype = ctypes.c_int32
+        L.pp_materialize_strings_utf16.argtypes = [P, ctypes.c_int64, P, ctypes.c_int32, ctypes.c_int32, P, P,
+                                                   ctypes.c_int64, P, ctypes.c_size_t, P]
         L.pp_workspace_size_utf16.restype = ctypes.c_size_t
         L.pp_workspace_size_utf16.argtypes = [ctypes.c_int64, P]
         L.pp_skip_records.restype = ctypes.c_int32
@@ -347,10 +350,13 @@ def parse(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
 
 
 def parse_utf16(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: int,
-                opts: Optional[PpOptions] = None, stream=None, reject_ragged: bool = False) -> Outputs:
+                opts: Optional[PpOptions] = None, stream=None, reject_ragged: bool = False,
+                control_bitmap: bool = False) -> Outputs:
     """pp_parse_utf16 (Sec. 4.2): parse the UTF-16LE text in the device
     tensor ``d_in`` (uint8 of even length, or int16/uint16 code units); every
-    position in the outputs is a byte offset into it. Asynchronous."""
+    position in the outputs is a byte offset into it. ``control_bitmap``:
+    also write the control-symbol bitmap (one bit per code unit), for
+    materialize_utf16. Asynchronous."""
     import torch
     if d_in.dtype == torch.uint8:
         if d_in.numel() % 2:
@@ -360,7 +366,8 @@ def parse_utf16(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: i
         n_units = int(d_in.numel())
     if stream is None:
         stream = torch.cuda.current_stream()
-    out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device)
+    out = alloc_outputs(types, cap_records, cap_fields, device=d_in.device,
+                        bitmap_bytes=n_units if control_bitmap else -1)
     ws = torch.empty(max(int(lib().pp_workspace_size_utf16(n_units, ctypes.byref(opts) if opts else None)), 1),
                      dtype=torch.uint8, device=d_in.device)
     call = Call(d_in, n_units, dfa, types, out, ws, opts, reject_ragged)
@@ -370,6 +377,32 @@ def parse_utf16(d_in, dfa, types: Sequence[int], cap_records: int, cap_fields: i
            "pp_parse_utf16")
     out._call = call  # keep the workspace alive until the caller synchronises
     return out
+
+
+def materialize_utf16(d_in, out: Outputs, column: int, cap_chars: Optional[int] = None, stream=None,
+                      terminator: int = -1):
+    """pp_materialize_strings_utf16: string column ``column`` of a
+    parse_utf16 parse (with control_bitmap=True) of ``d_in``, as (offsets
+    int64 [cap_records + 1] in code units, chars int16 code units).
+    Asynchronous."""
+    import torch
+    n_units = int(d_in.numel()) // 2 if d_in.dtype == torch.uint8 else int(d_in.numel())
+    if out.control_bitmap is None:
+        raise PpError("materialize_utf16: the parse did not write the control-symbol bitmap")
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    cap_chars = (n_units + (out.cap_records if terminator >= 0 else 0)) if cap_chars is None else int(cap_chars)
+    offsets = torch.empty(out.cap_records + 1, dtype=torch.int64, device=d_in.device)
+    chars = torch.empty(max(cap_chars, 1), dtype=torch.int16, device=d_in.device)
+    ws = torch.empty(max(int(lib().pp_materialize_workspace_size(n_units, out.cap_records)), 1), dtype=torch.uint8,
+                     device=d_in.device)
+    po, keep = _outputs_struct(out)
+    _check(lib().pp_materialize_strings_utf16(d_in.data_ptr() if n_units else None, n_units, ctypes.byref(po), column,
+                                              terminator, offsets.data_ptr(), chars.data_ptr(), cap_chars,
+                                              ws.data_ptr(), ws.numel(), ctypes.c_void_p(stream.cuda_stream)),
+           "pp_materialize_strings_utf16")
+    offsets._keep = (ws, keep)  # alive until the caller synchronises
+    return offsets, chars
 
 
 def infer_columns(d_in, dfa, opts: Optional[PpOptions] = None, stream=None) -> dict:

@@ -61,6 +61,9 @@ __device__ inline int64_t ctl_before(const uint32_t* bitmap, const int64_t* cp, 
     return c;
 }
 
+// SH: log2 of the bytes per symbol (0: bytes; 1: UTF-16 code units, whose
+// spans the parse gives in bytes)
+template <int SH>
 __global__ void value_lengths(const int64_t* begin, const int64_t* end, const uint8_t* valid, int64_t cap,
                               const pp_result_t* res, const uint32_t* bitmap, const int64_t* cp, int64_t* len,
                               int64_t* pieces, int64_t extra)
@@ -70,22 +73,23 @@ __global__ void value_lengths(const int64_t* begin, const int64_t* end, const ui
     for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < R; r += stride) {
         int64_t l = 0, p = 0;
         if (valid[r]) {
-            const int64_t b = begin[r], e = end[r];
+            const int64_t b = begin[r] >> SH, e = end[r] >> SH;
             if (e > b) {
                 l = (e - b) - (ctl_before(bitmap, cp, e) - ctl_before(bitmap, cp, b));
                 p = (e - b + kPiece - 1) / kPiece;
             }
         }
-        len[r] = l + extra;  // extra: the terminator byte of the inline-terminated form
+        len[r] = l + extra;  // extra: the terminator of the inline-terminated form
         pieces[r] = p;
     }
 }
 
-// one wavefront per piece of a value
-__global__ __launch_bounds__(256) void gather_pieces(const uint8_t* in, const int64_t* begin, const int64_t* end,
+// one wavefront per piece of a value; U: the symbol type (byte or code unit)
+template <typename U, int SH>
+__global__ __launch_bounds__(256) void gather_pieces(const U* in, const int64_t* begin, const int64_t* end,
                                                      int64_t cap, const pp_result_t* res, const uint32_t* bitmap,
                                                      const int64_t* cp, const int64_t* offsets,
-                                                     const int64_t* piece_off, uint8_t* chars, int64_t cap_chars)
+                                                     const int64_t* piece_off, U* chars, int64_t cap_chars)
 {
     const int64_t R = count_of(cap, res);
     const int64_t total = piece_off[R];
@@ -100,29 +104,30 @@ __global__ __launch_bounds__(256) void gather_pieces(const uint8_t* in, const in
             else hi = mid - 1;
         }
         const int64_t r = lo;
-        const int64_t b = begin[r], e = end[r];
+        const int64_t b = begin[r] >> SH, e = end[r] >> SH;
         const int64_t s0 = b + (q - piece_off[r]) * kPiece;
         const int64_t s1 = s0 + kPiece < e ? s0 + kPiece : e;
         int64_t out = offsets[r] + (s0 - b) - (ctl_before(bitmap, cp, s0) - ctl_before(bitmap, cp, b));
         for (int64_t i0 = s0; i0 < s1; i0 += 64) {
             const int64_t i = i0 + lane;
             bool data = false;
-            uint8_t byte = 0;
+            U sym = 0;
             if (i < s1) {
                 data = !((bitmap[i >> 5] >> (i & 31)) & 1u);
-                byte = in[i];
+                sym = in[i];
             }
             const uint64_t m = __ballot(data);
             const int64_t pos = out + __popcll(m & ((1ull << lane) - 1ull));
-            if (data && pos < cap_chars) chars[pos] = byte;
+            if (data && pos < cap_chars) chars[pos] = sym;
             out += __popcll(m);
         }
     }
 }
 
 // the inline-terminated form: the terminator after every value
-__global__ void terminate_values(const int64_t* offsets, int64_t cap, const pp_result_t* res, uint8_t* chars,
-                                 int64_t cap_chars, uint8_t term)
+template <typename U>
+__global__ void terminate_values(const int64_t* offsets, int64_t cap, const pp_result_t* res, U* chars,
+                                 int64_t cap_chars, U term)
 {
     const int64_t R = count_of(cap, res);
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -158,12 +163,14 @@ extern "C" size_t pp_materialize_workspace_size(int64_t n, int64_t cap_records)
     return ws_layout(n, cap_records).total;
 }
 
-extern "C" pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed,
-                                              int32_t column, int32_t terminator, int64_t* d_offsets,
-                                              uint8_t* d_chars, int64_t cap_chars, void* d_ws, size_t ws_bytes,
-                                              void* stream)
+namespace {
+
+// n: symbols (bytes, or code units); the offsets count symbols
+template <typename U, int SH>
+pp_status_t materialize(const U* d_in, int64_t n, const pp_outputs_t* parsed, int32_t column, int32_t terminator,
+                        int64_t* d_offsets, U* d_chars, int64_t cap_chars, void* d_ws, size_t ws_bytes, void* stream)
 {
-    if (terminator < -1 || terminator > 255) return PP_ERR_ARG;
+    if (terminator < -1 || terminator > (SH ? 0xffff : 0xff)) return PP_ERR_ARG;
     if (n < 0 || (n > 0 && !d_in) || !parsed || !parsed->d_result || !d_offsets || cap_chars < 0 ||
         (cap_chars > 0 && !d_chars) || !d_ws || column < 0 || column >= PP_MAX_COLUMNS)
         return PP_ERR_ARG;
@@ -196,17 +203,37 @@ extern "C" pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, co
         const int64_t* begin = (const int64_t*)parsed->d_values[column];
         const int64_t* end = parsed->d_str_end[column];
         const uint8_t* valid = parsed->d_valid[column];
-        hipLaunchKernelGGL(value_lengths, grid(cap), dim3(256), 0, s, begin, end, valid, cap, res, bm, cp, d_offsets,
-                           pieces, (int64_t)(terminator >= 0));
+        hipLaunchKernelGGL((value_lengths<SH>), grid(cap), dim3(256), 0, s, begin, end, valid, cap, res, bm, cp,
+                           d_offsets, pieces, (int64_t)(terminator >= 0));
         scan_i64(d_offsets, d_offsets, cap, res, partial, s);
         scan_i64(pieces, pieces, cap, res, partial, s);
-        hipLaunchKernelGGL(gather_pieces, dim3(2048), dim3(256), 0, s, d_in, begin, end, cap, res, bm, cp, d_offsets,
-                           pieces, d_chars, cap_chars);
+        hipLaunchKernelGGL((gather_pieces<U, SH>), dim3(2048), dim3(256), 0, s, d_in, begin, end, cap, res, bm, cp,
+                           d_offsets, pieces, d_chars, cap_chars);
         if (terminator >= 0)
-            hipLaunchKernelGGL(terminate_values, grid(cap), dim3(256), 0, s, d_offsets, cap, res, d_chars, cap_chars,
-                               (uint8_t)terminator);
+            hipLaunchKernelGGL((terminate_values<U>), grid(cap), dim3(256), 0, s, d_offsets, cap, res, d_chars,
+                               cap_chars, (U)terminator);
     } else {
         scan_i64(d_offsets, d_offsets, 0, res, partial, s);  // offsets[0] = 0
     }
     return hipGetLastError() == hipSuccess ? PP_OK : PP_ERR_HIP;
+}
+
+}  // namespace
+
+extern "C" pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outputs_t* parsed,
+                                              int32_t column, int32_t terminator, int64_t* d_offsets,
+                                              uint8_t* d_chars, int64_t cap_chars, void* d_ws, size_t ws_bytes,
+                                              void* stream)
+{
+    return materialize<uint8_t, 0>(d_in, n, parsed, column, terminator, d_offsets, d_chars, cap_chars, d_ws, ws_bytes,
+                                   stream);
+}
+
+extern "C" pp_status_t pp_materialize_strings_utf16(const uint16_t* d_in, int64_t n_units, const pp_outputs_t* parsed,
+                                                    int32_t column, int32_t terminator, int64_t* d_offsets,
+                                                    uint16_t* d_chars, int64_t cap_chars, void* d_ws, size_t ws_bytes,
+                                                    void* stream)
+{
+    return materialize<uint16_t, 1>(d_in, n_units, parsed, column, terminator, d_offsets, d_chars, cap_chars, d_ws,
+                                    ws_bytes, stream);
 }

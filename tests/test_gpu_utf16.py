@@ -7,7 +7,8 @@ every launch shape, text with non-ASCII characters (accented Latin, CJK,
 characters outside the BMP as surrogate pairs, a fullwidth comma that is
 data) across many tiles, numerals with non-ASCII digits, invalid input,
 empty and one-unit inputs, an input 2 bytes off 16-byte alignment, rejected
-ragged records and the tiles parsed out of order.
+ragged records and the tiles parsed out of order; and materialised string
+columns of UTF-16 text (pp_materialize_strings_utf16).
 """
 import random
 
@@ -83,3 +84,25 @@ def test_edges_alignment_rejection_and_order():
     same(b16, D.paper6(), types, tag="paper6 (invalid input)")
     for order in (1, 9):
         same(b16, D.csv4(), types, opts=pp.options(16, 256, order), tag=f"tile order {order}")
+
+
+@pytest.mark.parametrize("shape", [None, (16, 256)], ids=["512x64", "256x16"])
+def test_materialized_strings(shape):
+    """String columns of UTF-16 text materialised (control symbols removed,
+    code units kept), with and without a terminator code unit, against the
+    oracle's, including one quoted field far longer than a tile."""
+    o = pp.options(*shape) if shape else None
+    big = '1,"' + ("漢a,\n" * 40000) + '""q😀",x\n'
+    for b16 in (_text(7, 2000), _text(8, 40000), (big + "2,b,c\n").encode("utf-16-le")):
+        types = [D.STRING, D.STRING, D.STRING, D.STRING]
+        R, F = oracle.count(b16, D.csv4(), utf16=True)
+        d_in = torch.from_numpy(np.frombuffer(b16, dtype=np.uint8).copy()).cuda()
+        out = pp.parse_utf16(d_in, D.csv4(), types, R, F, opts=o, control_bitmap=True)
+        for c in range(4):
+            for term in (-1, 0x2028):
+                offs, chars = pp.materialize_utf16(d_in, out, c, terminator=term)
+                torch.cuda.synchronize()
+                want_o, want_c = oracle.materialize(b16, D.csv4(), c, terminator=term, utf16=True)
+                np.testing.assert_array_equal(offs.cpu().numpy()[:R + 1], want_o, err_msg=f"offsets {c} {term}")
+                got = chars.cpu().numpy().view(np.uint16)[:want_o[-1]]
+                np.testing.assert_array_equal(got, want_c, err_msg=f"chars {c} {term}")
