@@ -138,13 +138,14 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--profile-steps", type=int, default=0,
                     help="only run this many launches (for rocprofv3), no JSON")
-    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5", "stream"], default="c2",
+    ap.add_argument("--workload", choices=["c1", "c2", "c3", "c4", "c5", "stream", "utf16"], default="c2",
                     help="c1: 10,000-record RFC-4180 CSV, latency of one plain launch; "
                          "c2: 1 GiB numeric CSV, plain launch (default); "
                          "c3: 2 GiB text-heavy quoted CSV, plain launch; "
                          "c4: 4,096 mixed-dialect buffers, batched launch against plain launches; "
                          "c5: request loop over pinned host inputs, p50/p99 latency; "
-                         "stream: the 2 GiB text-heavy CSV end to end from pinned host memory in partitions")
+                         "stream: the 2 GiB text-heavy CSV end to end from pinned host memory in partitions; "
+                         "utf16: the 1 GiB numeric CSV as UTF-16LE text (2 GiB), pp_parse_utf16")
     ap.add_argument("--stream-partition", type=int, default=256 << 20, help="stream: partition bytes")
     ap.add_argument("--c5-requests", type=int, default=2000)
     ap.add_argument("--c5-pool-bytes", type=int, default=1 << 30,
@@ -167,6 +168,8 @@ def main():
         return bench_c5(args)
     if args.workload == "stream":
         return bench_stream(args)
+    if args.workload == "utf16":
+        return bench_utf16(args)
     return bench_plain(args)
 
 
@@ -718,6 +721,89 @@ def bench_c5(args):
         "roofline": {"bound": "pcie", "achieved": closed["sustained_gbs"], "peak": round(h2d_gbs, 2),
                      "unit": "GB/s", "frac": round(closed["sustained_gbs"] / h2d_gbs, 4), "traffic": None},
     }
+    print(json.dumps(line), flush=True)
+
+
+def bench_utf16(args):
+    """The 1 GiB numeric CSV widened to UTF-16LE (2 GiB, one code unit per
+    character), resident in HBM, parsed by pp_parse_utf16 (a narrowing pass,
+    the parse, the positions doubled). One step = one call."""
+    import ctypes
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_1905_13415_amd as pp
+    from datagen import dialects as D
+
+    g = datagen.c2()
+    types = list(D.SCHEMA_C2.types)
+    dfa = D.csv4()
+    units = g.data.astype(np.uint16)
+    n_units, R = len(units), g.nrecords
+    F = R * g.ncols
+    dev = torch.device("cuda:0")
+    d_in = torch.from_numpy(units.view(np.int16)).to(dev)
+    out = pp.alloc_outputs(types, R, F, device=dev)
+    L = pp.lib()
+    ws = torch.empty(int(L.pp_workspace_size_utf16(n_units, None)), dtype=torch.uint8, device=dev)
+    call = pp.Call(d_in, n_units, dfa, types, out, ws, None)
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        rc = L.pp_parse_utf16(d_in.data_ptr(), n_units, ctypes.byref(call.dfa), ctypes.byref(call.schema),
+                              ctypes.byref(call.outs), ws.data_ptr(), ws.numel(), None,
+                              ctypes.c_void_p(stream.cuda_stream))
+        if rc != pp.PP_OK:
+            raise pp.PpError(f"pp_parse_utf16: {rc}")
+
+    if args.profile_steps:
+        for _ in range(args.profile_steps):
+            launch()
+        torch.cuda.synchronize()
+        return
+    for _ in range(args.warmup):
+        launch()
+    torch.cuda.synchronize()
+    res = out.result_dict()
+    if res["status"] != pp.RESULT_OK or res["num_records"] != R or res["num_fields"] != F:
+        print(f"[bench] unexpected result {res}", file=sys.stderr)
+        sys.exit(1)
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    for a, b in evs:
+        a.record(stream)
+        launch()
+        b.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    per = sorted(a.elapsed_time(b) for a, b in evs)
+    ms = sum(per) / len(per)
+    nb = 2 * n_units
+    outb = output_bytes(R, F, types)
+    line = {
+        "metric": METRIC, "value": round(nb / (ms / 1e3) / 1e9, 2), "unit": "GB/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(wall * 1e3 / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u16",
+        "data": "synthetic (the seeded numeric CSV, one UTF-16 code unit per character; no dataset used)",
+        "config": {"workload": "utf16: the 1 GiB numeric CSV (c2) as UTF-16LE text, 2 GiB, 18 columns, csv4 DFA, "
+                               "pp_parse_utf16 on a resident buffer", "bytes": nb, "records": R, "fields": F},
+        "kernel_ms": {"mean": round(ms, 4), "median": round(per[len(per) // 2], 4), "min": round(per[0], 4),
+                      "max": round(per[-1], 4)},
+        "roofline": {"bound": "hbm", "achieved": round((nb + outb) / (ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
+                     "unit": "GB/s", "frac": round((nb + outb) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        t = time.perf_counter()
+        ref = oracle.parse(units.view(np.uint8), dfa, types, cap_records=R, cap_fields=F, utf16=True)
+        cpu_s = time.perf_counter() - t
+        assert ref.num_records == R
+        line["cpu_baseline"] = dict({"value": round(nb / cpu_s / 1e9, 4), "unit": "GB/s", "cores": 1, "kind": "oracle",
+                                     "sample": f"the whole {nb}-byte workload, one sequential oracle parse "
+                                               f"({cpu_s:.1f} s, outputs preallocated)"}, **host_cpu())
     print(json.dumps(line), flush=True)
 
 
