@@ -38,7 +38,7 @@ extern "C" {
 
 typedef int32_t pp_status_t;
 #define PP_OK 0
-#define PP_ERR_ARG (-1)         /* null pointer, negative size, bad option */
+#define PP_ERR_ARG (-1)         /* null pointer, negative size, bad option, misaligned workspace */
 #define PP_ERR_DFA (-2)         /* DFA out of range, invalid state not absorbing or = start */
 #define PP_ERR_SCHEMA (-3)      /* too many columns or unknown type */
 #define PP_ERR_WORKSPACE (-4)   /* workspace smaller than pp_workspace_size() */
@@ -166,7 +166,9 @@ typedef struct {
 } pp_options_t;
 
 /* Device scratch that pp_parse needs for an input of n bytes (tile counter
- * and the per-tile lookback words of the single-pass scans). */
+ * and the per-tile lookback words of the single-pass scans). Every d_ws
+ * argument of this library is device memory aligned to 256 bytes (as
+ * hipMalloc returns it); a misaligned one is PP_ERR_ARG. */
 size_t pp_workspace_size(int64_t n, const pp_options_t* opts);
 
 /*

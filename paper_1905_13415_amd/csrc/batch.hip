@@ -295,7 +295,7 @@ extern "C" pp_status_t pp_batch_bind(pp_batch_t* bt, void* d_ws, size_t ws_bytes
 pp_status_t pp::batch_bind_staged(pp_batch_t* bt, void* d_ws, size_t ws_bytes, void* h_stage, size_t stage_bytes,
                                   void* stream)
 {
-    if (!bt || !d_ws) return PP_ERR_ARG;
+    if (!bt || !d_ws || !ws_aligned(d_ws)) return PP_ERR_ARG;
     if (ws_bytes < bt->ws_size) return PP_ERR_WORKSPACE;
     char* ws = (char*)d_ws;
     // descriptors with device pointers into this workspace

@@ -5,6 +5,10 @@
 
 namespace pp {
 
+// Workspaces hold 64-bit atomics and 16-byte vectors: 256-byte alignment
+// (what hipMalloc returns) is required of every d_ws argument.
+inline bool ws_aligned(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
 // States and groups in range, every transition and tag in range, and an
 // invalid state (if any) that absorbs every symbol and is not the start state
 // (a run that starts there has no transition into it to report).

@@ -14,6 +14,7 @@
 #include <cstring>
 
 #include "convert.h"
+#include "dfa_check.h"
 #include "parparaw.h"
 
 namespace {
@@ -116,7 +117,7 @@ extern "C" pp_status_t pp_infer_types(const uint8_t* d_in, int64_t n, const pp_o
                                       void* stream)
 {
     if (n < 0 || (n > 0 && !d_in) || !parsed || !parsed->d_result || !d_types || !d_nonempty || !d_ws ||
-        ncols < 0 || ncols > PP_MAX_COLUMNS || parsed->cap_records < 0)
+        !pp::ws_aligned(d_ws) || ncols < 0 || ncols > PP_MAX_COLUMNS || parsed->cap_records < 0)
         return PP_ERR_ARG;
     if (ws_bytes < pp_infer_types_workspace_size(ncols)) return PP_ERR_WORKSPACE;
     if (ncols == 0) return PP_OK;

@@ -22,6 +22,7 @@
 
 #include <algorithm>
 
+#include "dfa_check.h"
 #include "parparaw.h"
 #include "scan.h"
 
@@ -172,7 +173,7 @@ pp_status_t materialize(const U* d_in, int64_t n, const pp_outputs_t* parsed, in
 {
     if (terminator < -1 || terminator > (SH ? 0xffff : 0xff)) return PP_ERR_ARG;
     if (n < 0 || (n > 0 && !d_in) || !parsed || !parsed->d_result || !d_offsets || cap_chars < 0 ||
-        (cap_chars > 0 && !d_chars) || !d_ws || column < 0 || column >= PP_MAX_COLUMNS)
+        (cap_chars > 0 && !d_chars) || !d_ws || !pp::ws_aligned(d_ws) || column < 0 || column >= PP_MAX_COLUMNS)
         return PP_ERR_ARG;
     const int64_t cap = parsed->cap_records;
     if (cap < 0) return PP_ERR_ARG;

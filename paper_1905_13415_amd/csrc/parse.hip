@@ -168,6 +168,7 @@ static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, const pp_dfa_t* df
                               void* stream, bool count_only)
 {
     if (n < 0 || (n > 0 && !d_in) || !schema || !out || !d_ws || !out->d_result) return PP_ERR_ARG;
+    if (!ws_aligned(d_ws)) return PP_ERR_ARG;
     Shape sh;
     if (!shape_of(opts, &sh)) return PP_ERR_ARG;
     if (out->cap_records < 0 || out->cap_fields < 0) return PP_ERR_ARG;

@@ -15,6 +15,7 @@
 
 #include <algorithm>
 
+#include "dfa_check.h"
 #include "parparaw.h"
 #include "scan.h"
 
@@ -153,8 +154,8 @@ extern "C" size_t pp_skip_rows_workspace_size(int64_t n)
 extern "C" pp_status_t pp_skip_rows(const uint8_t* d_in, int64_t n, const int64_t* ranges, int32_t nranges,
                                     uint8_t* d_out, int64_t* d_out_len, void* d_ws, size_t ws_bytes, void* stream)
 {
-    if (n < 0 || (n > 0 && (!d_in || !d_out)) || !d_out_len || !d_ws || nranges < 0 || nranges > kMaxRanges ||
-        (nranges > 0 && !ranges))
+    if (n < 0 || (n > 0 && (!d_in || !d_out)) || !d_out_len || !d_ws || !pp::ws_aligned(d_ws) || nranges < 0 ||
+        nranges > kMaxRanges || (nranges > 0 && !ranges))
         return PP_ERR_ARG;
     Ranges rg;
     rg.count = nranges;

@@ -96,6 +96,7 @@ extern "C" pp_status_t pp_parse_utf16(const uint16_t* d_in, int64_t n_units, con
                                       size_t ws_bytes, const pp_options_t* opts, void* stream)
 {
     if (n_units < 0 || (n_units > 0 && !d_in) || !schema || !out || !d_ws || !out->d_result) return PP_ERR_ARG;
+    if (!pp::ws_aligned(d_ws)) return PP_ERR_ARG;
     // everything pp_parse would reject is rejected before the narrowing runs
     const pp_status_t dst = pp::check_dfa_tables(dfa);
     if (dst != PP_OK) return dst;

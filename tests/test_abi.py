@@ -220,3 +220,21 @@ def test_utf16_argument_errors_without_device():
     assert call(wsb=ws - 1) == -4
     assert call(opts=pp.options(48, 256)) == -1
     assert call(opts=pp.options(0, 0, -2)) == -1
+
+
+def test_misaligned_workspace_is_an_argument_error():
+    """Every workspace argument must be 256-byte aligned (as hipMalloc
+    returns); a misaligned one is refused before any work is queued."""
+    good = pp.dfa_struct(D.csv4())
+    L = pp.lib()
+    t = (ctypes.c_int32 * 1)(0)
+    sch = pp.PpSchema(1, 0, ctypes.cast(t, ctypes.c_void_p))
+    ptrs = (ctypes.c_void_p * 64)(*([0x3000] * 64))
+    out = pp.PpOutputs(4, 4, 0x4000, 0x5000, 0x6000, ctypes.cast(ptrs, ctypes.c_void_p),
+                       ctypes.cast(ptrs, ctypes.c_void_p), ctypes.cast(ptrs, ctypes.c_void_p), 0x7000)
+    for off in (8, 64, 128):
+        assert L.pp_parse(0x1000, 16, ctypes.byref(good), ctypes.byref(sch), ctypes.byref(out), 0x2000 + off, 1 << 20,
+                          None, None) == -1
+        assert L.pp_parse_utf16(0x1000, 16, ctypes.byref(good), ctypes.byref(sch), ctypes.byref(out), 0x2000 + off,
+                                1 << 20, None, None) == -1
+        assert L.pp_skip_rows(0x1000, 16, None, 0, 0x8000, 0x9000, 0x2000 + off, 1 << 20, None) == -1
