@@ -726,8 +726,9 @@ def bench_c5(args):
 
 def bench_utf16(args):
     """The 1 GiB numeric CSV widened to UTF-16LE (2 GiB, one code unit per
-    character), resident in HBM, parsed by pp_parse_utf16 (a narrowing pass,
-    the parse, the positions doubled). One step = one call."""
+    character), resident in HBM, parsed by pp_parse_utf16 (the one tile
+    launch, narrowing the code units as it stages each tile). One step = one
+    call."""
     import ctypes
 
     import numpy as np

@@ -254,10 +254,12 @@ pp_status_t pp_materialize_strings(const uint8_t* d_in, int64_t n, const pp_outp
  * outputs (field offsets, string spans, the first invalid offset) is a byte
  * offset into d_in (twice the unit index); the control-symbol bitmap, when
  * requested, has one bit per code unit. Numbers, dates and times follow the
- * same grammars (ASCII digits). d_ws: pp_workspace_size_utf16(n_units, opts)
- * bytes (a one-byte-per-unit copy of the input, then pp_parse's workspace).
- * Errors as pp_parse, returned before any work is queued. Asynchronous on
- * stream; no allocation.
+ * same grammars (ASCII digits). One launch, as pp_parse: each tile's code
+ * units are narrowed to bytes as the tile is staged. d_ws:
+ * pp_workspace_size_utf16(n_units, opts) bytes (pp_parse's workspace for
+ * n_units symbols). Errors as pp_parse, returned before any work is queued;
+ * also PP_ERR_ARG for a d_in at an odd address. Asynchronous on stream; no
+ * allocation.
  */
 size_t pp_workspace_size_utf16(int64_t n_units, const pp_options_t* opts);
 /* Materialised string column of a pp_parse_utf16 parse (which wrote the

@@ -19,7 +19,7 @@ _ROOT = os.path.dirname(_HERE)
 LIB_PATH = os.path.join(_HERE, "libparparaw.so")
 SOURCES = [os.path.join(_HERE, "csrc", f) for f in ("parse.hip", "batch.hip", "serve.hip", "tune.hip", "copy.hip",
                                                      "stream.hip", "materialize.hip", "infer.hip",
-                                                     "rows.hip", "utf16.hip")]
+                                                     "rows.hip")]
 BUILD_DIR = os.path.join(_ROOT, "_build")
 
 PP_OK = 0

@@ -31,7 +31,7 @@ struct Params {
 // workspace: [ticket counter | pad] [byte tables, 4 KiB] [column descriptors] [kWordsPerTile words per tile]
 constexpr size_t kWsHeader = 256, kWsTables = 4096, kWsCols = PP_MAX_COLUMNS * sizeof(ColDesc);
 
-template <int NT, int B, bool NS8>
+template <int NT, int B, bool NS8, int SH>
 __global__ __launch_bounds__(NT) void parse_tiles(Params p)
 {
     __shared__ TileSmem<NT, B> sm;
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(NT) void parse_tiles(Params p)
         if (base + 64u <= (uint32_t)p.a.num_tiles)
             tile = base + (((2u * p.tile_order + 1u) * (tile & 63u) + 37u * p.tile_order) & 63u);
     }
-    parse_tile<NT, B, NS8, false>(p.a, tile, sm);
+    parse_tile<NT, B, NS8, false, SH>(p.a, tile, sm);
 }
 
 // Resets the workspace and the result before a parse; writes the outputs of
@@ -122,10 +122,16 @@ static bool shape_of(const pp_options_t* o, Shape* s)
 static pp_status_t check_dfa(const pp_dfa_t* d) { return check_dfa_tables(d); }
 
 template <int NT, int B>
-static void launch_tiles(const Params& p, bool ns8, int64_t tiles, hipStream_t s)
+static void launch_tiles(const Params& p, bool ns8, int sh, int64_t tiles, hipStream_t s)
 {
-    if (ns8) hipLaunchKernelGGL((parse_tiles<NT, B, true>), dim3((unsigned)tiles), dim3(NT), 0, s, p);
-    else hipLaunchKernelGGL((parse_tiles<NT, B, false>), dim3((unsigned)tiles), dim3(NT), 0, s, p);
+    const dim3 g((unsigned)tiles), b(NT);
+    if (sh) {
+        if (ns8) hipLaunchKernelGGL((parse_tiles<NT, B, true, 1>), g, b, 0, s, p);
+        else hipLaunchKernelGGL((parse_tiles<NT, B, false, 1>), g, b, 0, s, p);
+    } else {
+        if (ns8) hipLaunchKernelGGL((parse_tiles<NT, B, true, 0>), g, b, 0, s, p);
+        else hipLaunchKernelGGL((parse_tiles<NT, B, false, 0>), g, b, 0, s, p);
+    }
 }
 
 // The typed values of the records whose field count differs from ncols
@@ -161,20 +167,22 @@ extern "C" size_t pp_workspace_size(int64_t n, const pp_options_t* opts)
     return kWsHeader + kWsTables + kWsCols + (size_t)tiles * kWordsPerTile * sizeof(u64);
 }
 
-// The parse behind pp_parse and pp_infer_columns (count_only: no outputs
-// beyond the result record, never CAPACITY).
-static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, const pp_schema_t* schema,
+// The parse behind pp_parse, pp_parse_utf16 and pp_infer_columns (count_only:
+// no outputs beyond the result record, never CAPACITY). n symbols of
+// 1 << symsh bytes each.
+static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, int symsh, const pp_dfa_t* dfa, const pp_schema_t* schema,
                               const pp_outputs_t* out, void* d_ws, size_t ws_bytes, const pp_options_t* opts,
                               void* stream, bool count_only)
 {
     if (n < 0 || (n > 0 && !d_in) || !schema || !out || !d_ws || !out->d_result) return PP_ERR_ARG;
+    if (symsh && (((uintptr_t)d_in) & 1)) return PP_ERR_ARG;  // code units are 2-byte aligned
     if (!ws_aligned(d_ws)) return PP_ERR_ARG;
     Shape sh;
     if (!shape_of(opts, &sh)) return PP_ERR_ARG;
     if (out->cap_records < 0 || out->cap_fields < 0) return PP_ERR_ARG;
     if (!out->d_record_offsets || !out->d_field_offsets) return PP_ERR_ARG;
     if (out->cap_fields > 0 && !out->d_column_ids) return PP_ERR_ARG;
-    if (n >= (1ll << 55)) return PP_ERR_UNSUPPORTED;
+    if (n >= (1ll << (55 - symsh))) return PP_ERR_UNSUPPORTED;
     pp_status_t st = check_dfa(dfa);
     if (st != PP_OK) return st;
     if (schema->ncols < 0 || schema->ncols > PP_MAX_COLUMNS) return PP_ERR_SCHEMA;
@@ -248,11 +256,11 @@ static pp_status_t parse_impl(const uint8_t* d_in, int64_t n, const pp_dfa_t* df
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
     if (tiles == 0) return PP_OK;
     const bool ns8 = dfa->num_states > 4;
-    if (sh.nt == 512 && sh.b == 64) launch_tiles<512, 64>(p, ns8, tiles, s);
-    else if (sh.nt == 256 && sh.b == 64) launch_tiles<256, 64>(p, ns8, tiles, s);
-    else if (sh.nt == 256 && sh.b == 32) launch_tiles<256, 32>(p, ns8, tiles, s);
-    else if (sh.nt == 512 && sh.b == 32) launch_tiles<512, 32>(p, ns8, tiles, s);
-    else launch_tiles<256, 16>(p, ns8, tiles, s);
+    if (sh.nt == 512 && sh.b == 64) launch_tiles<512, 64>(p, ns8, symsh, tiles, s);
+    else if (sh.nt == 256 && sh.b == 64) launch_tiles<256, 64>(p, ns8, symsh, tiles, s);
+    else if (sh.nt == 256 && sh.b == 32) launch_tiles<256, 32>(p, ns8, symsh, tiles, s);
+    else if (sh.nt == 512 && sh.b == 32) launch_tiles<512, 32>(p, ns8, symsh, tiles, s);
+    else launch_tiles<256, 16>(p, ns8, symsh, tiles, s);
     if (hipGetLastError() != hipSuccess) return PP_ERR_HIP;
     if ((schema->flags & PP_SCHEMA_REJECT_RAGGED) && schema->ncols > 0 && out->cap_records > 0) {
         hipLaunchKernelGGL(reject_ragged, dim3(1024), dim3(256), 0, s, a);
@@ -265,7 +273,22 @@ extern "C" pp_status_t pp_parse(const uint8_t* d_in, int64_t n, const pp_dfa_t* 
                                 const pp_schema_t* schema, const pp_outputs_t* out, void* d_ws,
                                 size_t ws_bytes, const pp_options_t* opts, void* stream)
 {
-    return parse_impl(d_in, n, dfa, schema, out, d_ws, ws_bytes, opts, stream, false);
+    return parse_impl(d_in, n, 0, dfa, schema, out, d_ws, ws_bytes, opts, stream, false);
+}
+
+// UTF-16 text (Sec. 4.2): the same launch over code units, narrowed to bytes
+// as the tiles are staged; positions come out as byte offsets.
+extern "C" size_t pp_workspace_size_utf16(int64_t n_units, const pp_options_t* opts)
+{
+    return pp_workspace_size(n_units, opts);
+}
+
+extern "C" pp_status_t pp_parse_utf16(const uint16_t* d_in, int64_t n_units, const pp_dfa_t* dfa,
+                                      const pp_schema_t* schema, const pp_outputs_t* out, void* d_ws,
+                                      size_t ws_bytes, const pp_options_t* opts, void* stream)
+{
+    return parse_impl(reinterpret_cast<const uint8_t*>(d_in), n_units, 1, dfa, schema, out, d_ws, ws_bytes, opts,
+                      stream, false);
 }
 
 extern "C" pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp_dfa_t* dfa, pp_result_t* d_result,
@@ -281,7 +304,7 @@ extern "C" pp_status_t pp_infer_columns(const uint8_t* d_in, int64_t n, const pp
     o.d_field_offsets = (int64_t*)((char*)d_ws + 192);
     o.d_result = d_result;
     pp_schema_t sch = {0, 0, nullptr};
-    return parse_impl(d_in, n, dfa, &sch, &o, d_ws, ws_bytes, opts, stream, true);
+    return parse_impl(d_in, n, 0, dfa, &sch, &o, d_ws, ws_bytes, opts, stream, true);
 }
 
 // ---- entry point without allocation ---------------------------------------------

@@ -35,6 +35,15 @@
 //      count inference and validation, Sec. 4.3).
 // Tiles with more fields or records than the LDS staging holds take a
 // per-thread path for steps 6-7 that gives the same outputs.
+//
+// Symbols are bytes (SH = 0) or UTF-16 code units (SH = 1, Sec. 4.2). The
+// DFAs' structural symbols are ASCII, and a code unit below 0x80 is that
+// ASCII symbol while any other unit (both halves of a surrogate pair
+// included) can only be data; so the staging narrows each unit to one byte
+// (the unit itself below 0x80, else 0x80, which falls in the catch-all
+// group) and the pipeline runs on one byte per symbol, with tiles and chunks
+// holding whole code units by construction. Output positions are symbol
+// indices shifted left by SH: byte offsets into the input either way.
 // The input is read from HBM once; per-symbol metadata never leaves the chip;
 // outputs are written with streaming stores.
 #pragma once
@@ -421,6 +430,12 @@ __device__ inline Tot tot_from_agg(u64 a0, u64 a1, int64_t tile_start)
 // fields never start earlier).
 constexpr int kLdsBefore = 64;
 
+// A UTF-16 code unit as the byte the pipeline parses.
+__device__ __forceinline__ uint32_t narrow_unit(uint32_t u) { return u < 0x80u ? u : 0x80u; }
+
+// Symbol `pos` of the input as a byte: from LDS when the tile's copy holds
+// it, else from global memory (narrowed, for code units).
+template <int SH>
 struct ByteSrc {
     const uint8_t* lds;  // the tile; lds[-kLdsBefore, 0) hold the bytes before it
     const uint8_t* g;
@@ -428,15 +443,35 @@ struct ByteSrc {
     __device__ uint32_t operator()(int64_t pos) const
     {
         int64_t r = pos - tile_start;
-        return r >= -kLdsBefore ? lds[r] : gptr(g)[pos];
+        if (r >= -kLdsBefore) return lds[r];
+        if constexpr (SH) return narrow_unit(gptr(reinterpret_cast<const uint16_t*>(g))[pos]);
+        else return gptr(g)[pos];
     }
 };
+
+// Two code units narrowed in place: a packed 16-bit minimum with 0x80.
+__device__ __forceinline__ uint32_t narrow2(uint32_t w)
+{
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    const u16x2 cap = {0x80, 0x80};
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_min(__builtin_bit_cast(u16x2, w), cap));
+}
+
+// Eight code units (16 bytes) narrowed to eight bytes: the low bytes of the
+// narrowed pairs gathered. (The components are named: this compiler lowers a
+// bit cast of a subscripted vector element as element 0.)
+__device__ __forceinline__ uint2 narrow8(u32x4 v)
+{
+    return make_uint2(__builtin_amdgcn_perm(narrow2(v.y), narrow2(v.x), 0x06040200u),
+                      __builtin_amdgcn_perm(narrow2(v.w), narrow2(v.z), 0x06040200u));
+}
 
 // The general conversions (any length, any position, exponents, more than
 // 19 digits). Returns 1 converted, 0 not a value of the type. (Kept inline:
 // out of line, the calls cost the whole kernel about 7% on the numeric
 // workload.)
-__device__ inline int convert_general(int ty, const ByteSrc& src, int64_t b, int64_t e, u64* bits)
+template <class Src>
+__device__ inline int convert_general(int ty, const Src& src, int64_t b, int64_t e, u64* bits)
 {
     if (ty == PP_FLOAT64) {
         double dv = 0.0;
@@ -454,9 +489,10 @@ __device__ inline int convert_general(int ty, const ByteSrc& src, int64_t b, int
 }
 
 // Strip the enclosing control symbols of field [b, e) and convert it into
-// column c, record rec. ctl_first/ctl_last_sym: whether bytes b and e-1 are
+// column c, record rec. ctl_first/ctl_last_sym: whether symbols b and e-1 are
 // control symbols. Returns 1 on a conversion error.
-__device__ inline int store_field(const TileArgs& p, const ColDesc* cols, const ByteSrc& src, int c, int ty,
+template <int SH>
+__device__ inline int store_field(const TileArgs& p, const ColDesc* cols, const ByteSrc<SH>& src, int c, int ty,
                                   int64_t rec, int64_t b, int64_t e, bool ctl_first, bool ctl_last_sym)
 {
     int64_t begin = b, end = e;
@@ -466,8 +502,8 @@ __device__ inline int store_field(const TileArgs& p, const ColDesc* cols, const 
     const ColDesc cd = cols[c];
     if (ty == PP_STRING) {
         if (store) {
-            gptr((int64_t*)cd.values)[rec] = begin;
-            gptr(cd.str_end)[rec] = end;
+            gptr((int64_t*)cd.values)[rec] = begin << SH;
+            gptr(cd.str_end)[rec] = end << SH;
             gptr(cd.valid)[rec] = 1;
         }
         return 0;
@@ -564,8 +600,9 @@ __device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& s
 
 // The whole pipeline for tile `tile` of one buffer (steps 1-7 above).
 // SETUP: load the buffer's constants here (else the caller has, before a
-// barrier that precedes this call).
-template <int NT, int B, bool NS8, bool SETUP = true>
+// barrier that precedes this call). SH: symbols are bytes (0) or UTF-16
+// code units (1); p.n counts symbols.
+template <int NT, int B, bool NS8, bool SETUP = true, int SH = 0>
 __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t tile, TileSmem<NT, B>& sm)
 {
     static_assert(B == 16 || B == 32 || B == 64, "chunk bitmaps are one or two dwords");
@@ -618,7 +655,28 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     u64* const tw = p.words + (size_t)tile * kWordsPerTile;
 
     // ---- 1. stage the tile --------------------------------------------------------
-    {
+    if constexpr (SH) {  // code units, narrowed on the way into LDS
+        constexpr int PRE = TileSmem<NT, B>::PRE;
+        const uint16_t* src = reinterpret_cast<const uint16_t*>(p.in) + tile_start;
+        if (tile_len == TILE && (((uintptr_t)src) & 15) == 0) {
+            const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
+            uint2* d2 = reinterpret_cast<uint2*>(s_bytes);
+#pragma unroll
+            for (int k = tid; k < TILE / 8; k += NT) d2[k] = narrow8(__builtin_nontemporal_load(gptr(s4) + k));
+        } else {
+            for (int k = tid; k < TILE; k += NT) s_bytes[k] = k < tile_len ? narrow_unit(gptr(src)[k]) : 0;
+        }
+        if (tile_start >= PRE) {  // the symbols just before the tile
+            const uint16_t* pre = src - PRE;
+            if ((((uintptr_t)pre) & 15) == 0) {
+                if (tid < PRE / 8)
+                    reinterpret_cast<uint2*>(s_bytes - PRE)[tid] =
+                        narrow8(__builtin_nontemporal_load(gptr(reinterpret_cast<const u32x4*>(pre)) + tid));
+            } else if (tid < PRE) {
+                s_bytes[tid - PRE] = narrow_unit(gptr(pre)[tid]);
+            }
+        }
+    } else {
         const uint8_t* src = p.in + tile_start;
         if (tile_len == TILE && (((uintptr_t)src) & 15) == 0) {
             const u32x4* s4 = reinterpret_cast<const u32x4*>(src);
@@ -838,7 +896,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             r8 = step_state<NS8>(s_tcomb, cb_lds[i], r8);
             if (r8 == inv8) at = i;
         }
-        gptr(p.result)->first_invalid_offset = cstart + at;
+        gptr(p.result)->first_invalid_offset = (cstart + at) << SH;
     }
 
     auto popc = [](M m) -> uint32_t {
@@ -1037,7 +1095,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     const int64_t C0 = (int64_t)(readlane0_64(s_pref[2]) & kColVal);  // always absolute: seeded with (abs, 0)
     const u64 lastw = readlane0_64(s_pref[3]);
     const int ncols = p.ncols;
-    const ByteSrc src{s_bytes, p.in, tile_start};
+    const ByteSrc<SH> src{s_bytes, p.in, tile_start};
     const bool last_has = (lastw & kLastHas) != 0;
     const int64_t last_pos = (int64_t)(lastw & kLastPos);
     const uint32_t last_sa = (uint32_t)((lastw >> 56) & 0xf);
@@ -1049,7 +1107,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             const int r = (int)(b - tile_start);
             return (s_ctl[r >> 5] >> (r & 31)) & 1u;
         }
-        const uint32_t by = b >= tile_start - kLdsBefore ? s_bytes[b - tile_start] : gptr(p.in)[b];
+        const uint32_t by = src(b);
         // b follows the last delimiter before the tile, or is the buffer's
         // first byte (no delimiter before the tile), read in the start state
         const uint32_t s8 = (last_has ? last_sa : (uint32_t)p.start_state) * 8u;
@@ -1076,7 +1134,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             int32_t* const ci = p.column_ids + F0;
             const int open_end = Rt ? (int)s_recend[0] + 1 : Ft;  // fields of the record open at the tile start
             for (int k = tid; k < kf; k += NT) {
-                put(fo, (uint32_t)k, tile_start + 1 + s_pos[k]);
+                put(fo, (uint32_t)k, (tile_start + 1 + s_pos[k]) << SH);
                 put(ci, (uint32_t)k, (int32_t)s_colid[k] + (k < open_end ? (int32_t)C0 : 0));
             }
             const int64_t roomr = p.cap_records - R0;
@@ -1179,8 +1237,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 }
                 if (ty == PP_STRING) {
                     if (st) {
-                        put((int64_t*)vals, lr, tile_start + bb);
-                        put(ends, lr, tile_start + ee);
+                        put((int64_t*)vals, lr, (tile_start + bb) << SH);
+                        put(ends, lr, (tile_start + ee) << SH);
                         put(valid, lr, (uint8_t)1);
                     }
                 } else if (ee == bb) {  // empty: the column default, not an error
@@ -1244,7 +1302,7 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                 isrec = true;
             }
             const int64_t f = F0 + L;
-            if (f + 1 <= p.cap_fields) gptr(p.field_offsets)[f + 1] = pos + 1;
+            if (f + 1 <= p.cap_fields) gptr(p.field_offsets)[f + 1] = (pos + 1) << SH;
             if (f < p.cap_fields) gptr(p.column_ids)[f] = (int32_t)col;
             const int64_t rec = R0 + lr;
             if (col < ncols) {
