@@ -33,7 +33,8 @@ KERNEL_SOURCES = ["paper_1905_13415_amd/csrc/tile.h", "paper_1905_13415_amd/csrc
 # HBM byte counters of the dominant kernel per plain workload, from committed
 # rocprofv3 counter runs (not measured in this process)
 TRAFFIC_FILES = {"c2": "profiles/parse_tiles_c2_1GiB_traffic.json",
-                 "c3": "profiles/parse_tiles_c3_2GiB_traffic.json"}
+                 "c3": "profiles/parse_tiles_c3_2GiB_traffic.json",
+                 "utf16": "profiles/parse_tiles_utf16_2GiB_traffic.json"}
 METRIC = "on-device parse GB/s & % of HBM roofline; batched/serving vs plain; p50/p99 latency"
 
 
@@ -763,6 +764,11 @@ def bench_utf16(args):
         for _ in range(args.profile_steps):
             launch()
         torch.cuda.synchronize()
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)  # the byte counters' reference copy
+        dst = torch.empty_like(src)
+        pp.copy(dst, src, stream=stream)
+        torch.cuda.synchronize()
+        print("[bench] profile launches done (plus one 1 GiB streaming copy)", file=sys.stderr, flush=True)
         return
     for _ in range(args.warmup):
         launch()
@@ -793,9 +799,15 @@ def bench_utf16(args):
                                "pp_parse_utf16 on a resident buffer", "bytes": nb, "records": R, "fields": F},
         "kernel_ms": {"mean": round(ms, 4), "median": round(per[len(per) // 2], 4), "min": round(per[0], 4),
                       "max": round(per[-1], 4)},
+        "output_bytes": outb,
         "roofline": {"bound": "hbm", "achieved": round((nb + outb) / (ms / 1e3) / 1e9, 1), "peak": HBM_PEAK_GBS,
-                     "unit": "GB/s", "frac": round((nb + outb) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None},
+                     "unit": "GB/s", "frac": round((nb + outb) / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4),
+                     "traffic": measured_traffic("utf16"),
+                     "timing": "HIP events on the launch stream around each call, mean over the timed steps",
+                     "traffic_source": TRAFFIC_FILES["utf16"]},
     }
+    tr = line["roofline"]["traffic"]
+    line["roofline"]["traffic_frac"] = round(tr / (ms / 1e3) / 1e9 / HBM_PEAK_GBS, 4) if tr else None
     if not args.no_cpu_baseline:
         import oracle
         t = time.perf_counter()

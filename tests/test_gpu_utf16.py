@@ -7,8 +7,10 @@ every launch shape, text with non-ASCII characters (accented Latin, CJK,
 characters outside the BMP as surrogate pairs, a fullwidth comma that is
 data) across many tiles, numerals with non-ASCII digits, invalid input,
 empty and one-unit inputs, an input 2 bytes off 16-byte alignment, rejected
-ragged records and the tiles parsed out of order; and materialised string
-columns of UTF-16 text (pp_materialize_strings_utf16).
+ragged records and the tiles parsed out of order; every path of the tile
+kernel (per-thread fields, fields and numbers that begin before the tile's
+LDS copy, invalid input); and materialised string columns of UTF-16 text
+(pp_materialize_strings_utf16).
 """
 import random
 
@@ -84,6 +86,39 @@ def test_edges_alignment_rejection_and_order():
     same(b16, D.paper6(), types, tag="paper6 (invalid input)")
     for order in (1, 9):
         same(b16, D.csv4(), types, opts=pp.options(16, 256, order), tag=f"tile order {order}")
+
+
+TILE = 512 * 64  # code units per tile of the default launch shape
+
+
+def test_tile_paths():
+    """The code-unit form through every path of the tile kernel: every
+    symbol a delimiter (more fields than a tile stages: the per-thread
+    path), a quoted field of non-ASCII text spanning tiles, numbers spanning
+    tiles (converted from units read and narrowed outside the tile's LDS
+    copy), the first field of a tile beginning at offsets around the 64
+    units kept before the tile, and invalid input deep in the text."""
+    t3 = [D.INT64, D.STRING, D.FLOAT64]
+    for ch in (",", "\n"):
+        same((ch * (3 * TILE + 5)).encode("utf-16-le"), D.csv4(), t3, tag=f"all {ch!r}")
+    body = "".join(random.Random(1).choice('ab,\n é漢😀""') for _ in range(2 * TILE))
+    for dfa in (D.csv4(), D.paper6()):
+        same(('1,"' + body + '",2\n3,"x",4\n').encode("utf-16-le"), dfa, t3, tag="long quoted field")
+    same(("7," + "0" * (2 * TILE + 100) + "42,x\n1.5," + "9" * 30000 + ",y\n").encode("utf-16-le"), D.csv4(),
+         [D.FLOAT64, D.INT64, D.STRING], tag="long numbers")
+    first = "p" * 10 + ",1,2.5\n"
+    for head in ("-1234567", '"q,u""o"', "é"):
+        for d in (0, 1, 63, 64, 65, 100, 300):
+            # field 1 of the second record begins d units before the second tile
+            pad = TILE - d - len(first) - 1
+            text = first + "漢" * pad + "," + head + ",2.5\n" + "1,2,3.5\n" * 50
+            assert text.find(head, len(first)) == TILE - d
+            for types in ([D.STRING, D.INT64, D.FLOAT64], [D.INT64, D.STRING, D.FLOAT64]):
+                same(text.encode("utf-16-le"), D.csv4(), types, tag=f"{head!r} at -{d}")
+    data = bytearray(datagen.c1().data[:5 * TILE])
+    data[3 * TILE + 100] = ord('"')  # a quote in an unquoted field: invalid under paper6
+    ref = same(widen(data), D.paper6(), D.SCHEMA_C1.types, tag="invalid")
+    assert ref.first_invalid_offset >= 0
 
 
 @pytest.mark.parametrize("shape", [None, (16, 256)], ids=["512x64", "256x16"])
