@@ -151,6 +151,58 @@ __device__ __forceinline__ int ser_float64(const Win& x, int len, double* out, c
     return 1;
 }
 
+// Per byte of a word: 0x80 where the byte is zero (exact: no carries
+// between bytes), and 0x80 where the byte is above 9.
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t y)
+{
+    return ~(((y & 0x7f7f7f7fu) + 0x7f7f7f7fu) | y | 0x7f7f7f7fu);
+}
+__device__ __forceinline__ uint32_t above9_bytes(uint32_t t)
+{
+    return (((t & 0x7f7f7f7fu) + 0x76767676u) | t) & 0x80808080u;
+}
+
+// ser_float64 for a field of at most 8 bytes, with word-parallel steps in
+// place of the byte loop (same grammar, same results) and no branches: a
+// sign reads as a leading zero digit; the field is right-aligned in a 64-bit
+// word with the ASCII '0' bits cleared (digits become their values, the
+// bytes shifted in are leading zeros, bytes past the field drop out); a
+// decimal point is found by an exact per-byte zero test, every other byte
+// must be at most 9, the point's byte is squeezed out by shifting the bytes
+// before it up one, and the eight digits (at most 10^8 - 1, so the range
+// checks always pass) are combined by 8-bit dot products. Without a point
+// the division is by 10^0 = 1, which is exact.
+__device__ __forceinline__ int ser_float64_8(const Win& x, int len, double* out, const double* pow10)
+{
+    typedef unsigned long long u64;
+    const uint32_t c0 = x.w[0] & 0xffu;
+    const bool neg = c0 == '-';
+    const uint32_t k = c0 - 0x2bu;  // '+' and '-' are 0x2b and 0x2d: bits 0 and 2 of 5
+    const bool sg = ((0x5u >> (k & 31u)) & (k < 3u ? 1u : 0u)) != 0u;
+    const uint32_t w0 = (x.w[0] & ~0xffu) | (sg ? 0x30u : c0);
+    const u64 raw = ((u64)(x.w[1] ^ 0x30303030u) << 32) | (w0 ^ 0x30303030u);
+    const u64 t = raw << (64u - 8u * (uint32_t)len);  // len in [1, 8]
+    const uint32_t tl = (uint32_t)t, th = (uint32_t)(t >> 32);
+    const uint32_t zl = zero_bytes(tl ^ 0x1e1e1e1eu), zh = zero_bytes(th ^ 0x1e1e1e1eu);  // '.' ^ '0' = 0x1e
+    const uint32_t bad = (above9_bytes(tl) & ~zl) | (above9_bytes(th) & ~zh);
+    const int ndot = __popc(zl) + __popc(zh);
+    const int nd = len - (int)sg - ndot;
+    const uint32_t pz = zl ? (uint32_t)__builtin_ctz(zl) : 32u + (uint32_t)__builtin_ctz(zh | 0x80000000u);
+    const uint32_t p = pz >> 3;  // the point's byte (7 when there is none: unused)
+    const u64 after = (~0ull << (8u * p)) << 8;  // the bytes after the point
+    const u64 d = ndot ? ((t & after) | ((t << 8) & ~after)) : t;
+    const int frac = ndot ? 7 - (int)p : 0;
+    const uint32_t lo = (uint32_t)d, hi = (uint32_t)(d >> 32);
+    // byte 0 is the most significant digit: d0*100 + d1*10 + d2, then *10 + d3
+    const uint32_t a = __builtin_amdgcn_udot4(lo, 0x00010a64u, 0u, false);
+    const uint32_t b = __builtin_amdgcn_udot4(hi, 0x00010a64u, 0u, false);
+    const uint32_t ha = __builtin_amdgcn_udot4(lo, 0x01000000u, __umul24(a, 10u), false);
+    const uint32_t hb = __builtin_amdgcn_udot4(hi, 0x01000000u, __umul24(b, 10u), false);
+    const double v = (double)(__umul24(ha, 10000u) + hb) / pow10[frac];
+    *out = neg ? -v : v;
+    return (bad != 0u || ndot > 1) ? -1 : (nd > 0 ? 1 : 0);
+}
+
 // Fixed-layout date and time fields: every digit and separator is checked
 // and the results are combined with & (no short-circuit branches).
 __device__ __forceinline__ uint32_t win_num(const Win& x, int p, int n, bool& ok)

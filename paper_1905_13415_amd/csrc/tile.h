@@ -1254,7 +1254,8 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                         const Win x = load_win_lazy(words, bb, len);
                         if (ty == PP_FLOAT64) {
                             double dv = 0.0;
-                            r = ser_float64(x, len, &dv, sm.pow10);
+                            r = wave_any(len > 8) ? ser_float64(x, len, &dv, sm.pow10)
+                                                  : ser_float64_8(x, len, &dv, sm.pow10);
                             bits = __builtin_bit_cast(u64, dv);
                         } else {
                             int64_t iv = 0;

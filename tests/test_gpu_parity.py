@@ -246,6 +246,24 @@ def test_hard_floats():
     assert_same(u8(data), D.csv4(), [D.FLOAT64, D.INT64])
 
 
+def test_short_float_fields_every_form():
+    """Float fields of at most 8 bytes take a word-parallel parse (a wavefront
+    whose fields are all that short): every field of up to 4 symbols over
+    digits, point, signs, an exponent letter and a space, and random fields of
+    5-8 such symbols, with no longer field in the column, against the oracle
+    (values, validity and the conversion-error count)."""
+    import itertools
+    alpha = "0123456789.-+e "
+    vals = ["".join(t) for n in range(1, 4) for t in itertools.product(alpha, repeat=n)]
+    rnd = random.Random(8)
+    vals += ["".join(rnd.choice(alpha) for _ in range(4)) for _ in range(20000)]
+    vals += ["".join(rnd.choice("0123456789.-+") for _ in range(rnd.randint(5, 8))) for _ in range(60000)]
+    vals += ["-" + "".join(rnd.choice("0123456789") for _ in range(6)) + "." for _ in range(2000)]
+    assert max(map(len, vals)) <= 8
+    data = "".join(f"{v},{i}\n" for i, v in enumerate(vals)).encode()
+    assert_same(u8(data), D.csv4(), [D.FLOAT64, D.INT64])
+
+
 INTS = ["0", "-0", "+7", "9223372036854775807", "-9223372036854775808", "9223372036854775808",
         "-9223372036854775809", "00000000000000000000042", "", "+", "-", "1 ", " 1", "1.0", "12a",
         "99999999999999999999"]
