@@ -93,6 +93,19 @@ def test_tiny_records_fallback_and_mixed_tiles(shape):
     assert_same(u8(data), D.csv4(), [D.INT64, D.INT64], opts=opts_of(shape))
 
 
+@pytest.mark.parametrize("shape", [None, (16, 256)], ids=["512x64", "256x16"])
+def test_wide_records_column_ids_past_254(shape):
+    """Records of 250-600 fields of 7 bytes: few enough fields per tile for
+    the LDS staging, but column ids past 254 (the staged 8-bit ids' limit)
+    send a tile to the per-thread path; records of exactly 255 fields (ids
+    0-254) stay staged. Mixed with short records so both paths meet."""
+    t = [D.INT64, D.STRING, D.FLOAT64, D.INT64]
+    for nf in (250, 254, 255, 256, 257, 300, 600):
+        rec = ",".join(f"{i:06d}" for i in range(nf)) + "\n"
+        data = (rec * (3 * TILE // len(rec) + 2) + "1,a,2.5,3\n" * 4000 + rec * 7).encode()
+        assert_same(u8(data), D.csv4(), t, opts=opts_of(shape))
+
+
 def test_long_quoted_field_spanning_tiles():
     body = bytes(random.Random(1).choice(b'ab,\n ') for _ in range(5 * TILE))
     data = b'1,"' + body + b'",2\n3,"x",4\n'
