@@ -68,7 +68,7 @@ __device__ __forceinline__ T load_uniform(const T* p)
 // persistent loop over tickets was measured to raise register use from 105
 // to 176 VGPRs, halving occupancy, for no gain.)
 template <int NT, int B, bool NS8>
-__global__ __launch_bounds__(NT) void batch_tiles(BatchParams bp)
+__global__ __launch_bounds__(NT, 4) void batch_tiles(BatchParams bp)
 {
     __shared__ TileSmem<NT, B> sm;
     __shared__ uint32_t s_ticket;

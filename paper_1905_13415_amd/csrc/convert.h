@@ -194,6 +194,8 @@ __device__ inline void dec_shl(Decimal& a, int k)
     dec_trim(a);
 }
 
+__device__ __forceinline__ double dec_to_double(Decimal& a, bool neg);
+
 template <class Src>
 __device__ __noinline__ double float_slow(const Src& src, int64_t b, int64_t e)
 {
@@ -229,6 +231,13 @@ __device__ __noinline__ double float_slow(const Src& src, int64_t b, int64_t e)
             if (ex < 100000000) ex = ex * 10 + (src(i) - '0');
         a.dp += (int)(eneg ? -ex : ex);
     }
+    return dec_to_double(a, neg);
+}
+
+// The binary64 nearest to the decimal a (ties to even), negated if neg. a
+// holds the significant digits as read (trailing zeros included).
+__device__ __forceinline__ double dec_to_double(Decimal& a, bool neg)
+{
     dec_trim(a);
     const double sgn = neg ? -1.0 : 1.0;
     if (a.nd == 0) return sgn * 0.0;

@@ -32,7 +32,7 @@ struct Params {
 constexpr size_t kWsHeader = 256, kWsTables = 4096, kWsCols = PP_MAX_COLUMNS * sizeof(ColDesc);
 
 template <int NT, int B, bool NS8, int SH>
-__global__ __launch_bounds__(NT) void parse_tiles(Params p)
+__global__ __launch_bounds__(NT, 4) void parse_tiles(Params p)
 {
     __shared__ TileSmem<NT, B> sm;
     __shared__ uint32_t s_ticket;

@@ -430,6 +430,19 @@ __device__ inline Tot tot_from_agg(u64 a0, u64 a1, int64_t tile_start)
 // fields never start earlier).
 constexpr int kLdsBefore = 64;
 
+// A numeric field that begins tiles back and is at least this many symbols
+// long is converted after the tile's own conversion by the whole workgroup
+// (the block-level collaboration of Sec. 3.3) instead of by one lane
+// reading it symbol by symbol from HBM. (A field within the tile is shorter
+// than a tile and its lane reads it from LDS.)
+constexpr int64_t kLongField = 2048;
+struct LongEntry {
+    int64_t b, e, rec;  // symbol span (enclosing control symbols stripped), global record
+    uint32_t meta;      // column | type << 16
+    uint32_t pad;
+};
+constexpr int kDigCap = 800;  // significant digits a long float keeps (the slow path's Decimal)
+
 // A UTF-16 code unit as the byte the pipeline parses.
 __device__ __forceinline__ uint32_t narrow_unit(uint32_t u) { return u < 0x80u ? u : 0x80u; }
 
@@ -559,6 +572,19 @@ struct TileSmem {
     uint32_t wsv[NW][2];
     Cnt wcnt[NW];
     uint32_t anyctl, s0, fin, last_sa, guess, colovf;
+    // Long numeric fields queued for the workgroup pass: the tile's first
+    // field when it is a number that began tiles back (fields within the
+    // tile are shorter than a tile and read from LDS by their lane).
+    static constexpr int LCAP = 1;
+    LongEntry longq[LCAP];
+    uint32_t nlong;
+    u64 red[8];  // the pass's reductions
+    // the buffer's input, record capacity and column descriptors for the
+    // pass, kept here rather than in registers across the whole tile
+    const uint8_t* lin;
+    int64_t lcap;
+    const ColDesc* lcols;
+    pp_result_t* lres;
     u64 pref[4];
     u64 err, ragged, fmin, fmax;  // fmin/fmax: fewest/most fields of a record closed here
 };
@@ -596,6 +622,320 @@ __device__ __forceinline__ void tile_setup(const TileArgs& p, TileSmem<NT, B>& s
         sm.after_delim[b] = (uint8_t)(any && same ? a : 0xffu);
         sm.ctl_any[b] = (uint8_t)ctl;
     }
+}
+
+// ---- long numeric fields: the workgroup pass ----------------------------------------
+__device__ inline u64 wave_min_u64(u64 v)
+{
+#pragma unroll
+    for (int d = 32; d; d >>= 1) {
+        const u64 o = shfl_xor64(v, d);
+        v = o < v ? o : v;
+    }
+    return v;
+}
+__device__ inline u64 wave_max_u64(u64 v)
+{
+#pragma unroll
+    for (int d = 32; d; d >>= 1) {
+        const u64 o = shfl_xor64(v, d);
+        v = o > v ? o : v;
+    }
+    return v;
+}
+__device__ inline u64 wave_sum_u64(u64 v)
+{
+#pragma unroll
+    for (int d = 32; d; d >>= 1) v += shfl_xor64(v, d);
+    return v;
+}
+__device__ inline uint32_t word_of(const u32x4& v, int q) { return q == 0 ? v.x : q == 1 ? v.y : q == 2 ? v.z : v.w; }
+
+// The symbols [lo, hi) of the input, spread over the workgroup: those at the
+// unaligned ends one at a time to sym_visit(i, c) (c the symbol's byte),
+// the aligned middle four at a time to word_visit(i, w) (symbols i..i+3 as
+// the bytes of w, low byte first), from 16-byte loads (two in flight per
+// thread).
+template <int NT, int SH, class SymVisit, class WordVisit>
+__device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, SymVisit&& sym_visit,
+                                    WordVisit&& word_visit)
+{
+    const int tid = threadIdx.x;
+    auto sym = [&](int64_t i) -> uint32_t {
+        if constexpr (SH) return narrow_unit(gptr(reinterpret_cast<const uint16_t*>(in))[i]);
+        else return gptr(in)[i];
+    };
+    if (hi <= lo) return;
+    const uintptr_t base = (uintptr_t)in;
+    const uintptr_t a = base + ((uintptr_t)lo << SH), z = base + ((uintptr_t)hi << SH);
+    const uintptr_t a16 = (a + 15) & ~(uintptr_t)15, z16 = z & ~(uintptr_t)15;
+    if (a16 >= z16) {
+        for (int64_t i = lo + tid; i < hi; i += NT) sym_visit(i, sym(i));
+        return;
+    }
+    const int64_t h1 = (int64_t)((a16 - base) >> SH), t0 = (int64_t)((z16 - base) >> SH);
+    for (int64_t i = lo + tid; i < h1; i += NT) sym_visit(i, sym(i));
+    for (int64_t i = t0 + tid; i < hi; i += NT) sym_visit(i, sym(i));
+    constexpr int SPB = 16 >> SH;  // symbols per 16-byte block
+    const int64_t nblk = (int64_t)((z16 - a16) >> 4);
+    const u32x4* const blk = reinterpret_cast<const u32x4*>(a16);
+    for (int64_t k0 = tid; k0 < nblk; k0 += 2 * NT) {
+        const int64_t k1 = k0 + NT;
+        const u32x4 v0 = __builtin_nontemporal_load(gptr(blk) + k0);
+        const u32x4 v1 = k1 < nblk ? __builtin_nontemporal_load(gptr(blk) + k1) : u32x4{0u, 0u, 0u, 0u};
+        auto block = [&](const u32x4& v, int64_t k) {
+            const int64_t i0 = h1 + k * SPB;
+            if constexpr (SH) {
+                const uint2 n = narrow8(v);
+                word_visit(i0, n.x);
+                word_visit(i0 + 4, n.y);
+            } else {
+                word_visit(i0, v.x);
+                word_visit(i0 + 4, v.y);
+                word_visit(i0 + 8, v.z);
+                word_visit(i0 + 12, v.w);
+            }
+        };
+        block(v0, k0);
+        if (k1 < nblk) block(v1, k1);
+    }
+}
+
+// Per byte of a word of symbols, 0x80 where: not a digit; the digit '0'; a
+// decimal point; an exponent mark (e or E). Exact per byte.
+__device__ inline uint32_t nondigit_bytes(uint32_t w) { return above9_bytes(w ^ 0x30303030u); }
+__device__ inline uint32_t zerodigit_bytes(uint32_t w) { return zero_bytes(w ^ 0x30303030u); }
+__device__ inline uint32_t point_bytes(uint32_t w) { return zero_bytes(w ^ 0x2e2e2e2eu); }
+__device__ inline uint32_t expmark_bytes(uint32_t w) { return zero_bytes((w | 0x20202020u) ^ 0x65656565u); }
+__device__ inline int64_t first_byte(uint32_t f) { return __builtin_ctz(f) >> 3; }
+__device__ inline int64_t last_byte(uint32_t f) { return (31 - __builtin_clz(f)) >> 3; }
+
+// Converts the queued long numeric fields, one at a time, with the whole
+// workgroup (every thread calls this): the field's symbols are classified
+// in parallel and the facts the sequential conversions depend on are reduced
+// -- for INT64 the grammar and the first nonzero digit; for FLOAT64 the
+// exponent mark, the decimal point, the grammar, the first and last nonzero
+// mantissa digits and the first nonzero exponent digit -- and the first
+// kDigCap significant digits gathered in LDS. One thread then finishes with
+// the same arithmetic as conv_int64 / conv_float64 (Clinger's exact case, or
+// the Decimal of the slow path built from the gathered digits), so every
+// result equals the sequential conversion's. Stores the value and validity
+// of records within the capacity and adds the conversion errors to the
+// tile's count.
+template <int NT, int B, int SH>
+__device__ __noinline__ void long_pass(TileSmem<NT, B>& sm)
+{
+    const uint8_t* const in = sm.lin;
+    const int64_t cap_records = sm.lcap;
+    const ColDesc* const cols = sm.lcols;
+    constexpr u64 NONE = ~0ull;
+    const int tid = threadIdx.x, lane = tid & 63;
+    const uint32_t nl = sm.nlong < (uint32_t)TileSmem<NT, B>::LCAP ? sm.nlong : (uint32_t)TileSmem<NT, B>::LCAP;
+    uint8_t* const dig = reinterpret_cast<uint8_t*>(sm.pos);  // free once the tile's conversion is done
+    static_assert(TileSmem<NT, B>::FCAP * 2 >= kDigCap, "digit buffer");
+    auto sym = [&](int64_t i) -> uint32_t {
+        if constexpr (SH) return narrow_unit(gptr(reinterpret_cast<const uint16_t*>(in))[i]);
+        else return gptr(in)[i];
+    };
+    auto rmin = [&](int k, u64 v) {
+        v = wave_min_u64(v);
+        if (lane == 0 && v != NONE) atomicMin((unsigned long long*)&sm.red[k], (unsigned long long)v);
+    };
+    auto rmax = [&](int k, u64 v) {
+        v = wave_max_u64(v);
+        if (lane == 0 && v) atomicMax((unsigned long long*)&sm.red[k], (unsigned long long)v);
+    };
+    auto rsum = [&](int k, u64 v) {
+        v = wave_sum_u64(v);
+        if (lane == 0 && v) atomicAdd((unsigned long long*)&sm.red[k], (unsigned long long)v);
+    };
+    u64 errs = 0;
+    for (uint32_t q = 0; q < nl; ++q) {
+        const LongEntry en = sm.longq[q];
+        const uint32_t ty = en.meta >> 16, col = en.meta & 0xffffu;
+        const int64_t b = en.b, e = en.e;
+        const uint32_t c0 = sym(b);
+        const bool neg = c0 == '-', sg = neg || c0 == '+';
+        const int64_t s0 = b + (sg ? 1 : 0);
+        if (tid < 8) sm.red[tid] = (tid == 0 || tid == 4 || tid == 7) ? NONE : 0ull;
+        __syncthreads();
+        int ok = 0;
+        u64 bits = 0;
+        if (ty == PP_INT64) {
+            // [+-]?[0-9]+: any other symbol (red[1]), the first nonzero digit (red[0])
+            u64 bad = 0, fnz = NONE;
+            scan_symbols<NT, SH>(
+                in, s0, e,
+                [&](int64_t i, uint32_t c) {
+                    bad |= (u64)(c - '0' > 9u);
+                    if (c - '1' < 9u && (u64)i < fnz) fnz = (u64)i;
+                },
+                [&](int64_t i, uint32_t w) {
+                    const uint32_t nd = nondigit_bytes(w), nz = ~nd & ~zerodigit_bytes(w) & 0x80808080u;
+                    bad |= (u64)(nd != 0u);
+                    if (nz && (u64)(i + first_byte(nz)) < fnz) fnz = (u64)(i + first_byte(nz));
+                });
+            rsum(1, bad);
+            rmin(0, fnz);
+            __syncthreads();
+            if (tid == 0) {
+                const u64 f = sm.red[0];
+                if (s0 < e && sm.red[1] == 0) {
+                    if (f == NONE) {
+                        ok = 1;  // all zeros
+                    } else if (e - (int64_t)f <= 19) {  // more significant digits overflow
+                        const uint64_t limit = neg ? (1ull << 63) : (1ull << 63) - 1;
+                        uint64_t mag = 0;
+                        ok = 1;
+                        for (int64_t i = (int64_t)f; i < e; ++i) {
+                            const uint32_t d = sym(i) - '0';
+                            if (mag > (limit - d) / 10u) { ok = 0; break; }
+                            mag = mag * 10u + d;
+                        }
+                        if (ok) bits = neg ? 0ull - mag : mag;
+                    }
+                }
+            }
+        } else {
+            // the exponent mark: the first e or E after the sign (red[0])
+            u64 em = NONE;
+            scan_symbols<NT, SH>(
+                in, s0, e,
+                [&](int64_t i, uint32_t c) {
+                    if ((c | 0x20u) == 'e' && (u64)i < em) em = (u64)i;
+                },
+                [&](int64_t i, uint32_t w) {
+                    const uint32_t m = expmark_bytes(w);
+                    if (m && (u64)(i + first_byte(m)) < em) em = (u64)(i + first_byte(m));
+                });
+            rmin(0, em);
+            __syncthreads();
+            const int64_t E = sm.red[0] == NONE ? e : (int64_t)sm.red[0];
+            // mantissa [s0, E): points (count red[1], place red[2] + 1),
+            // other symbols (red[3]), first (red[4]) and last (red[5] + 1)
+            // nonzero digit; exponent digits from x0: others (red[6]),
+            // first nonzero (red[7])
+            const bool esg = E + 1 < e && ((sym(E + 1) == '+') || (sym(E + 1) == '-'));
+            const int64_t x0 = E + 1 + (esg ? 1 : 0);
+            u64 ndot = 0, dpos = 0, nbad = 0, fnz = NONE, lnz = 0;
+            scan_symbols<NT, SH>(
+                in, s0, E,
+                [&](int64_t i, uint32_t c) {
+                    const bool d = c - '0' < 10u, dot = c == '.';
+                    ndot += dot;
+                    if (dot) dpos = (u64)i + 1;
+                    nbad += !d && !dot;
+                    if (c - '1' < 9u) {
+                        fnz = (u64)i < fnz ? (u64)i : fnz;
+                        lnz = (u64)i + 1 > lnz ? (u64)i + 1 : lnz;
+                    }
+                },
+                [&](int64_t i, uint32_t w) {
+                    const uint32_t nd = nondigit_bytes(w), pt = point_bytes(w);
+                    const uint32_t nz = ~nd & ~zerodigit_bytes(w) & 0x80808080u;
+                    ndot += (u64)__popc(pt);
+                    if (pt) dpos = (u64)(i + last_byte(pt)) + 1;
+                    nbad += (u64)__popc(nd & ~pt);
+                    if (nz) {
+                        const u64 f = (u64)(i + first_byte(nz)), l = (u64)(i + last_byte(nz)) + 1;
+                        fnz = f < fnz ? f : fnz;
+                        lnz = l > lnz ? l : lnz;
+                    }
+                });
+            u64 ebad = 0, efnz = NONE;
+            if (E < e)
+                scan_symbols<NT, SH>(
+                    in, x0, e,
+                    [&](int64_t i, uint32_t c) {
+                        ebad |= (u64)(c - '0' > 9u);
+                        if (c - '1' < 9u && (u64)i < efnz) efnz = (u64)i;
+                    },
+                    [&](int64_t i, uint32_t w) {
+                        const uint32_t nd = nondigit_bytes(w), nz = ~nd & ~zerodigit_bytes(w) & 0x80808080u;
+                        ebad |= (u64)(nd != 0u);
+                        if (nz && (u64)(i + first_byte(nz)) < efnz) efnz = (u64)(i + first_byte(nz));
+                    });
+            rsum(1, ndot);
+            rmax(2, dpos);
+            rsum(3, nbad);
+            rmin(4, fnz);
+            rmax(5, lnz);
+            rsum(6, ebad);
+            rmin(7, efnz);
+            __syncthreads();
+            const u64 ndots = sm.red[1], F = sm.red[4];
+            const int64_t dotpos = ndots ? (int64_t)sm.red[2] - 1 : E;  // the point, or E without one
+            const int64_t L = (int64_t)sm.red[5] - 1;                  // the last nonzero digit
+            const bool valid = sm.red[3] == 0 && ndots <= 1 && (E - s0 - (int64_t)ndots) >= 1 &&
+                               (E == e || (x0 < e && sm.red[6] == 0));
+            // significant digits from the first nonzero one, the point skipped
+            auto sigidx = [&](int64_t i) -> int64_t { return (i - (int64_t)F) - (ndots && dotpos > (int64_t)F && dotpos < i ? 1 : 0); };
+            if (valid && F != NONE) {
+                for (int64_t i = (int64_t)F + tid; i < E && i < (int64_t)F + kDigCap + 1; i += NT) {
+                    const uint32_t c = sym(i);
+                    if (c != '.') {
+                        const int64_t k = sigidx(i);
+                        if (k < kDigCap) dig[k] = (uint8_t)(c - '0');
+                    }
+                }
+            }
+            __syncthreads();
+            if (tid == 0 && valid) {
+                ok = 1;
+                if (F == NONE) {
+                    bits = neg ? (1ull << 63) : 0ull;  // a signed zero
+                } else {
+                    // the exponent as the sequential loops read it: digits
+                    // accumulate while the value is below 10^8, so the first
+                    // (at most nine) significant ones count
+                    int64_t ex = 0;
+                    if (E < e && sm.red[7] != NONE)
+                        for (int64_t i = (int64_t)sm.red[7]; i < e && ex < 100000000; ++i) ex = ex * 10 + (sym(i) - '0');
+                    if (esg && sym(E + 1) == '-') ex = -ex;
+                    const int64_t nS = (E - (int64_t)F) - (ndots && dotpos > (int64_t)F ? 1 : 0);
+                    const int64_t nint = (int64_t)F < dotpos ? dotpos - (int64_t)F : 0;  // significant integer digits
+                    const int64_t nfrac = ndots ? E - dotpos - 1 : 0;
+                    const int64_t last = sigidx(L);
+                    uint64_t w = 0;
+                    for (int64_t k = 0; k < nS && k < 19; ++k) w = w * 10 + dig[k];
+                    const int64_t dropped = nint > 19 ? nint - 19 : 0;
+                    int64_t kept = 0;
+                    if (ndots && nint < 19) {
+                        if ((int64_t)F > dotpos) {
+                            const int64_t lz = (int64_t)F - dotpos - 1;
+                            kept = lz + (nfrac - lz < 19 ? nfrac - lz : 19);
+                        } else {
+                            kept = nfrac < 19 - nint ? nfrac : 19 - nint;
+                        }
+                    }
+                    const int64_t e10 = ex + dropped - kept;
+                    if (last < 19 && w <= (1ull << 53) && e10 >= -22 && e10 <= 22) {
+                        double v = (double)w;
+                        v = e10 < 0 ? v / exact_pow10((int)-e10) : v * exact_pow10((int)e10);
+                        bits = __builtin_bit_cast(u64, neg ? -v : v);
+                    } else {
+                        Decimal a;
+                        a.nd = (int)(nS < kDecCap ? nS : kDecCap);
+                        for (int k = 0; k < a.nd; ++k) a.d[k] = dig[k];
+                        a.trunc = last >= kDecCap;
+                        a.dp = (int)((int64_t)F < dotpos ? nint : -((int64_t)F - dotpos - 1));
+                        a.dp += (int)ex;
+                        bits = __builtin_bit_cast(u64, dec_to_double(a, neg));
+                    }
+                }
+            }
+        }
+        if (tid == 0) {
+            if (en.rec < cap_records) {
+                const ColDesc cd = cols[col];
+                gptr((u64*)cd.values)[en.rec] = ok ? bits : 0ull;
+                gptr(cd.valid)[en.rec] = (uint8_t)ok;
+            }
+            errs += !ok;
+        }
+        __syncthreads();  // red and the digits are reused by the next field
+    }
+    if (tid == 0 && errs) atomicAdd((u64*)&sm.lres->num_conversion_errors, errs);
 }
 
 // The whole pipeline for tile `tile` of one buffer (steps 1-7 above).
@@ -641,6 +981,11 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
     // read before the staging barrier.
     if (tid == 0) {
         sm.colovf = 0;
+        sm.nlong = 0;
+        sm.lin = p.in;
+        sm.lcap = p.cap_records;
+        sm.lcols = p.cols;
+        sm.lres = p.result;
         s_anyctl = 0;
         s_err = 0;
         s_ragged = 0;
@@ -1215,6 +1560,14 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
                     if (hb < tile_start - kLdsBefore) {  // begins further back than LDS holds: general path
                         const bool cfst = e > hb && ctl_at_begin(hb);
                         const bool clst = e > hb && ctl_at_end(e);
+                        if ((ty == PP_INT64 || ty == PP_FLOAT64) && e - hb >= kLongField) {
+                            // a long number (it began tiles back): the workgroup
+                            // pass converts and stores it (one such field per tile)
+                            sm.longq[0] = LongEntry{hb + (int64_t)cfst, e - (int64_t)clst, R0 + lr,
+                                                    c | (ty << 16), 0u};
+                            sm.nlong = 1u;
+                            continue;
+                        }
                         nerr += store_field(p, s_cols, src, (int)c, (int)ty, R0 + lr, hb, e, cfst, clst);
                         continue;
                     }
@@ -1378,6 +1731,9 @@ __device__ __forceinline__ void parse_tile(const TileArgs& p, const uint32_t til
             res->status = st;
         }
     }
+    // Last, so that nothing of the tile stays live across the call:
+    // workgroup-uniform (LDS written before the barrier above).
+    if (sm.nlong) long_pass<NT, B, SH>(sm);
 }
 
 }  // namespace pp

@@ -15,6 +15,7 @@ import numpy as np
 import pytest
 
 import datagen
+import oracle
 import paper_1905_13415_amd as pp
 from datagen import dialects as D
 from parity import assert_same, gpu_parse
@@ -125,6 +126,80 @@ def test_one_field_of_200mb():
     data = u8(b'1,"' + txt + b'",2.5\n2,"a""b",3\n3,short,4.25\n')
     assert txt.count(b'""') > 100000
     assert_same(data, D.csv4(), [D.INT64, D.STRING, D.FLOAT64])
+
+
+def _long_numeric_fields(rnd):
+    """Integer and float fields of 2,048 symbols or more (converted by the
+    workgroup pass) in every form the grammar decides on: leading zeros,
+    signs, overflow at the 19-digit boundary, long fractions, more than 800
+    significant digits with and without a nonzero digit past the 800th,
+    exponents with leading zeros or beyond 10^8, and each way of breaking the
+    grammar."""
+    z = lambda k: "0" * k
+    digits = lambda k: "".join(rnd.choice("0123456789") for _ in range(k))
+    ints = [z(5000) + "42", "-" + z(3000) + "7", "+" + z(2500), z(2047) + "1", "1" + z(2100),
+            z(4000) + "9223372036854775807", z(4000) + "9223372036854775808",
+            "-" + z(4000) + "9223372036854775808", "-" + z(4000) + "9223372036854775809",
+            z(3000) + "12x4", z(2100) + "-5", z(3000) + "1.0", z(2600) + " "]
+    floats = [z(5000) + "42.5", "-" + z(3000) + ".000" + z(2000) + "15", "0." + z(2400) + "1e2405",
+              "1." + digits(3000), digits(2100) + "." + digits(900), digits(2500),
+              "0.5" + z(2000) + "1", "0.5" + z(3000), "2." + z(850) + z(1500) + "1",
+              "1.0000000000000002220446049250313080847263336181640625" + z(2500),
+              "1.0000000000000002220446049250313080847263336181640625" + z(2500) + "1",
+              "1e" + z(3000) + "22", "1e+" + z(2400) + "308", "1e-" + z(2400) + "330", "7e" + "9" * 2100,
+              "-" + z(2300) + "e5", z(2200) + ".", "." + z(2200), "." + z(2200) + "3",
+              z(2200) + "1..5", z(2200) + "1e5e5", z(2200) + "1e", z(2200) + "1e+", z(2200) + "1x",
+              "+" + z(2200) + "-1", z(2300) + "E-" + z(5) + "3", digits(1000) + "." + digits(1500) + "e-" + z(2000) + "1200"]
+    return ints, floats
+
+
+@pytest.mark.parametrize("shape", [None, (16, 256)], ids=["512x64", "256x16"])
+def test_long_numeric_fields_workgroup_pass(shape):
+    """Numeric fields of 2,048 symbols or more: those that begin tiles back
+    (a tile's first field) are converted by the whole workgroup after the
+    tile's own conversion, those within a tile by their lane from LDS, and
+    those in tiles with more fields than the staging holds by the per-thread
+    path; every value, validity and the error count against the oracle."""
+    rnd = random.Random(12)
+    ints, floats = _long_numeric_fields(rnd)
+    rows = []
+    for k in range(max(len(ints), len(floats))):
+        rows.append(f"{ints[k % len(ints)]},{floats[k % len(floats)]},{k}\n")
+        rows.append(f"{k},{k}.5,{k}\n" * rnd.randint(0, 40))
+    data = "".join(rows).encode()
+    types = [D.INT64, D.FLOAT64, D.INT64]
+    assert_same(u8(data), D.csv4(), types, opts=opts_of(shape))
+    # a tile with more fields than it stages holds a long integer and float
+    crowd = ("," * 9000 + "\n") + "".join(f"{i},{f},1\n" for i, f in zip(ints, floats))
+    assert_same(u8(crowd.encode() * 3), D.csv4(), types, opts=opts_of(shape))
+    # quoted long numbers (control symbols stripped before the conversion)
+    quoted = "".join(f'"{i}","{f}",2\n' for i, f in zip(ints, floats)).encode()
+    assert_same(u8(quoted), D.csv4(), types, opts=opts_of(shape))
+
+
+def test_long_numeric_fields_utf16():
+    """The same fields as UTF-16 text (the pass reads and narrows code units)."""
+    rnd = random.Random(13)
+    ints, floats = _long_numeric_fields(rnd)
+    text = "".join(f"{i},{f},{k}\n" for k, (i, f) in enumerate(zip(ints * 2, floats)))
+    b16 = text.encode("utf-16-le")
+    ref = oracle.parse(b16, D.csv4(), [D.INT64, D.FLOAT64, D.INT64], utf16=True)
+    d_in = torch.from_numpy(np.frombuffer(b16, dtype=np.uint8).copy()).cuda()
+    out = pp.parse_utf16(d_in, D.csv4(), [D.INT64, D.FLOAT64, D.INT64], ref.num_records, ref.num_fields)
+    torch.cuda.synchronize()
+    from parity import compare
+    compare(ref, out, out.result_dict(), [D.INT64, D.FLOAT64, D.INT64], tag="utf16 long numbers")
+
+
+def test_one_numeric_field_of_20mb():
+    """A float of 20 million digits and an integer of 20 million leading
+    zeros, each one field spanning hundreds of tiles, converted by the
+    workgroup of the tile that closes it, equal to the oracle's."""
+    rng = np.random.default_rng(5)
+    frac = rng.integers(48, 58, size=20_000_000, dtype=np.uint8).tobytes()
+    data = b"1,2.5,3\n" + b"7," + b"3." + frac + b",9\n" + b"0" * 20_000_000 + b"42,1.25,8\n" + b"4,5,6\n"
+    assert_same(u8(data), D.csv4(), [D.INT64, D.FLOAT64, D.INT64])
+    assert_same(u8(data), D.csv4(), [D.FLOAT64, D.FLOAT64, D.INT64])
 
 
 def test_long_numeric_field_spanning_tiles():
