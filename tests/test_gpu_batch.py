@@ -46,7 +46,11 @@ def _extras():
     csv4_comma = [d.name for d in dfas].index("csv4")
     rnd = random.Random(9)
     soup = bytes(rnd.choice(b'\n",ab1.-') for _ in range(70000))
+    # numbers that begin tiles back (converted by the workgroup pass)
+    digits = bytes(rnd.choice(b"0123456789") for _ in range(90000))
+    longnum = b"1,2.5\n" + b"0" * 70000 + b"42,3." + digits + b"\n-" + b"0" * 40000 + b"7,1e" + b"0" * 50000 + b"5\n5,6\n"
     return [
+        (np.frombuffer(longnum, np.uint8), csv4_comma, [D.INT64, D.FLOAT64]),        # long numbers
         (np.zeros(0, np.uint8), csv4_comma, [D.INT64, D.STRING]),                     # empty
         (np.frombuffer(b"7", np.uint8), csv4_comma, [D.INT64]),                       # one byte
         (np.frombuffer(b"," * 70000, np.uint8), csv4_comma, [D.INT64, D.STRING]),     # per-thread path
