@@ -654,7 +654,7 @@ __device__ inline uint32_t word_of(const u32x4& v, int q) { return q == 0 ? v.x 
 // The symbols [lo, hi) of the input, spread over the workgroup: those at the
 // unaligned ends one at a time to sym_visit(i, c) (c the symbol's byte),
 // the aligned middle four at a time to word_visit(i, w) (symbols i..i+3 as
-// the bytes of w, low byte first), from 16-byte loads (two in flight per
+// the bytes of w, low byte first), from 16-byte loads (four in flight per
 // thread).
 template <int NT, int SH, class SymVisit, class WordVisit>
 __device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, SymVisit&& sym_visit,
@@ -679,10 +679,13 @@ __device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, S
     constexpr int SPB = 16 >> SH;  // symbols per 16-byte block
     const int64_t nblk = (int64_t)((z16 - a16) >> 4);
     const u32x4* const blk = reinterpret_cast<const u32x4*>(a16);
-    for (int64_t k0 = tid; k0 < nblk; k0 += 2 * NT) {
-        const int64_t k1 = k0 + NT;
-        const u32x4 v0 = __builtin_nontemporal_load(gptr(blk) + k0);
-        const u32x4 v1 = k1 < nblk ? __builtin_nontemporal_load(gptr(blk) + k1) : u32x4{0u, 0u, 0u, 0u};
+    for (int64_t k0 = tid; k0 < nblk; k0 += 4 * NT) {
+        u32x4 v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int64_t k = k0 + (int64_t)u * NT;
+            v[u] = k < nblk ? __builtin_nontemporal_load(gptr(blk) + k) : u32x4{0u, 0u, 0u, 0u};
+        }
         auto block = [&](const u32x4& v, int64_t k) {
             const int64_t i0 = h1 + k * SPB;
             if constexpr (SH) {
@@ -696,8 +699,9 @@ __device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, S
                 word_visit(i0 + 12, v.w);
             }
         };
-        block(v0, k0);
-        if (k1 < nblk) block(v1, k1);
+#pragma unroll
+        for (int u = 0; u < 4; ++u)
+            if (k0 + (int64_t)u * NT < nblk) block(v[u], k0 + (int64_t)u * NT);
     }
 }
 

@@ -202,6 +202,33 @@ def test_one_numeric_field_of_20mb():
     assert_same(u8(data), D.csv4(), [D.FLOAT64, D.FLOAT64, D.INT64])
 
 
+def test_one_numeric_field_of_200mb():
+    """The skewed input of the paper's evaluation as a number: one float
+    field of 200 million digits between short records, equal to the
+    oracle's, and converted by the closing tile's workgroup within half a
+    second (one lane reading it symbol by symbol from HBM takes seconds)."""
+    rng = np.random.default_rng(6)
+    frac = rng.integers(48, 58, size=200_000_000, dtype=np.uint8).tobytes()
+    data = u8(b"1,2.5\n7,3." + frac + b"\n4,5.25\n")
+    types = [D.INT64, D.FLOAT64]
+    assert_same(data, D.csv4(), types)
+    d_in = torch.from_numpy(data).cuda()
+    out = pp.alloc_outputs(types, 3, 6)
+    ws = torch.empty(pp.workspace_size(len(data)), dtype=torch.uint8, device="cuda")
+    call = pp.Call(d_in, len(data), D.csv4(), types, out, ws)
+    call.launch(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    t0, t1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0.record()
+    call.launch(torch.cuda.current_stream())
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1)
+    print(f"200 MB float field: {ms:.2f} ms")
+    assert out.result_dict()["num_conversion_errors"] == 0
+    assert ms < 500.0
+
+
 def test_long_numeric_field_spanning_tiles():
     data = b"7," + b"0" * (2 * TILE + 100) + b"42,x\n" + b"1.5," + b"9" * 30000 + b",y\n"
     assert_same(u8(data), D.csv4(), [D.FLOAT64, D.INT64, D.STRING])
