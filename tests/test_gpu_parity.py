@@ -175,6 +175,10 @@ def test_long_numeric_fields_workgroup_pass(shape):
     # quoted long numbers (control symbols stripped before the conversion)
     quoted = "".join(f'"{i}","{f}",2\n' for i, f in zip(ints, floats)).encode()
     assert_same(u8(quoted), D.csv4(), types, opts=opts_of(shape))
+    # a long number closed by the end of input, and records past the capacity
+    tail = ("1,2.5,3\n" * 10 + "4,5.5," + "0" * 70000 + "6").encode()
+    assert_same(u8(tail), D.csv4(), types, opts=opts_of(shape))
+    assert_same(u8(data), D.csv4(), types, opts=opts_of(shape), cap_records=30, cap_fields=100)
 
 
 def test_long_numeric_fields_utf16():
