@@ -169,6 +169,7 @@ def test_long_numeric_fields_workgroup_pass(shape):
     data = "".join(rows).encode()
     types = [D.INT64, D.FLOAT64, D.INT64]
     assert_same(u8(data), D.csv4(), types, opts=opts_of(shape))
+    assert_same(u8(data), D.paper6(), types, opts=opts_of(shape))  # a 6-state DFA (8-state vectors)
     # a tile with more fields than it stages holds a long integer and float
     crowd = ("," * 9000 + "\n") + "".join(f"{i},{f},1\n" for i, f in zip(ints, floats))
     assert_same(u8(crowd.encode() * 3), D.csv4(), types, opts=opts_of(shape))
