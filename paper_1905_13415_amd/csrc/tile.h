@@ -578,7 +578,7 @@ struct TileSmem {
     static constexpr int LCAP = 1;
     LongEntry longq[LCAP];
     uint32_t nlong;
-    u64 red[8];  // the pass's reductions
+    u64 red[12];  // the pass's reductions
     // the buffer's input, record capacity and column descriptors for the
     // pass, kept here rather than in registers across the whole tile
     const uint8_t* lin;
@@ -655,7 +655,7 @@ __device__ inline uint32_t word_of(const u32x4& v, int q) { return q == 0 ? v.x 
 // unaligned ends one at a time to sym_visit(i, c) (c the symbol's byte),
 // the aligned middle four at a time to word_visit(i, w) (symbols i..i+3 as
 // the bytes of w, low byte first), from 16-byte loads (four in flight per
-// thread).
+// thread). Each thread visits its symbols in increasing position.
 template <int NT, int SH, class SymVisit, class WordVisit>
 __device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, SymVisit&& sym_visit,
                                     WordVisit&& word_visit)
@@ -675,7 +675,6 @@ __device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, S
     }
     const int64_t h1 = (int64_t)((a16 - base) >> SH), t0 = (int64_t)((z16 - base) >> SH);
     for (int64_t i = lo + tid; i < h1; i += NT) sym_visit(i, sym(i));
-    for (int64_t i = t0 + tid; i < hi; i += NT) sym_visit(i, sym(i));
     constexpr int SPB = 16 >> SH;  // symbols per 16-byte block
     const int64_t nblk = (int64_t)((z16 - a16) >> 4);
     const u32x4* const blk = reinterpret_cast<const u32x4*>(a16);
@@ -703,6 +702,7 @@ __device__ inline void scan_symbols(const uint8_t* in, int64_t lo, int64_t hi, S
         for (int u = 0; u < 4; ++u)
             if (k0 + (int64_t)u * NT < nblk) block(v[u], k0 + (int64_t)u * NT);
     }
+    for (int64_t i = t0 + tid; i < hi; i += NT) sym_visit(i, sym(i));
 }
 
 // Per byte of a word of symbols, 0x80 where: not a digit; the digit '0'; a
@@ -761,7 +761,7 @@ __device__ __noinline__ void long_pass(TileSmem<NT, B>& sm)
         const uint32_t c0 = sym(b);
         const bool neg = c0 == '-', sg = neg || c0 == '+';
         const int64_t s0 = b + (sg ? 1 : 0);
-        if (tid < 8) sm.red[tid] = (tid == 0 || tid == 4 || tid == 7) ? NONE : 0ull;
+        if (tid < 12) sm.red[tid] = (tid == 0 || tid == 7 || tid == 8) ? NONE : 0ull;
         __syncthreads();
         int ok = 0;
         u64 bits = 0;
@@ -801,77 +801,107 @@ __device__ __noinline__ void long_pass(TileSmem<NT, B>& sm)
                 }
             }
         } else {
-            // the exponent mark: the first e or E after the sign (red[0])
-            u64 em = NONE;
+            // One pass over [s0, e) classifies every symbol: exponent marks
+            // (first red[0], count red[1]), points (count red[2], last
+            // red[3] + 1), other symbols (red[4]), signs (count red[5], last
+            // red[6] + 1), nonzero digits (first red[8], last red[9] + 1).
+            // A valid field has at most one mark E, signs only right after
+            // it, no point after it; then the nonzero digits before E are
+            // the mantissa's and only the exponent's digits (usually few)
+            // and, when they hold a nonzero digit, the mantissa's last
+            // nonzero digit need another pass.
+            u64 em = NONE, ne = 0, ndot = 0, dpos = 0, nbad = 0, nsg = 0, spos = 0, fnz = NONE, lnz = 0;
             scan_symbols<NT, SH>(
                 in, s0, e,
                 [&](int64_t i, uint32_t c) {
-                    if ((c | 0x20u) == 'e' && (u64)i < em) em = (u64)i;
-                },
-                [&](int64_t i, uint32_t w) {
-                    const uint32_t m = expmark_bytes(w);
-                    if (m && (u64)(i + first_byte(m)) < em) em = (u64)(i + first_byte(m));
-                });
-            rmin(0, em);
-            __syncthreads();
-            const int64_t E = sm.red[0] == NONE ? e : (int64_t)sm.red[0];
-            // mantissa [s0, E): points (count red[1], place red[2] + 1),
-            // other symbols (red[3]), first (red[4]) and last (red[5] + 1)
-            // nonzero digit; exponent digits from x0: others (red[6]),
-            // first nonzero (red[7])
-            const bool esg = E + 1 < e && ((sym(E + 1) == '+') || (sym(E + 1) == '-'));
-            const int64_t x0 = E + 1 + (esg ? 1 : 0);
-            u64 ndot = 0, dpos = 0, nbad = 0, fnz = NONE, lnz = 0;
-            scan_symbols<NT, SH>(
-                in, s0, E,
-                [&](int64_t i, uint32_t c) {
-                    const bool d = c - '0' < 10u, dot = c == '.';
+                    const bool d = c - '0' < 10u, dot = c == '.', mk = (c | 0x20u) == 'e', sgn = c == '+' || c == '-';
+                    ne += mk;
+                    if (mk && (u64)i < em) em = (u64)i;
                     ndot += dot;
-                    if (dot) dpos = (u64)i + 1;
-                    nbad += !d && !dot;
+                    if (dot && (u64)i + 1 > dpos) dpos = (u64)i + 1;
+                    nsg += sgn;
+                    if (sgn && (u64)i + 1 > spos) spos = (u64)i + 1;
+                    nbad += !d && !dot && !mk && !sgn;
                     if (c - '1' < 9u) {
                         fnz = (u64)i < fnz ? (u64)i : fnz;
                         lnz = (u64)i + 1 > lnz ? (u64)i + 1 : lnz;
                     }
                 },
                 [&](int64_t i, uint32_t w) {
-                    const uint32_t nd = nondigit_bytes(w), pt = point_bytes(w);
-                    const uint32_t nz = ~nd & ~zerodigit_bytes(w) & 0x80808080u;
-                    ndot += (u64)__popc(pt);
-                    if (pt) dpos = (u64)(i + last_byte(pt)) + 1;
-                    nbad += (u64)__popc(nd & ~pt);
-                    if (nz) {
-                        const u64 f = (u64)(i + first_byte(nz)), l = (u64)(i + last_byte(nz)) + 1;
-                        fnz = f < fnz ? f : fnz;
-                        lnz = l > lnz ? l : lnz;
+                    const uint32_t nd = nondigit_bytes(w), nz = ~nd & ~zerodigit_bytes(w) & 0x80808080u;
+                    if (nz) {  // positions increase: the first is the least, the latest the greatest
+                        if (fnz == NONE) fnz = (u64)(i + first_byte(nz));
+                        lnz = (u64)(i + last_byte(nz)) + 1;
                     }
+                    if (nd == 0u) return;  // four digits (the common word)
+                    const uint32_t pt = point_bytes(w), mk = expmark_bytes(w);
+                    const uint32_t sg = zero_bytes(w ^ 0x2b2b2b2bu) | zero_bytes(w ^ 0x2d2d2d2du);
+                    if (mk) {
+                        ne += (u64)__popc(mk);
+                        const u64 f = (u64)(i + first_byte(mk));
+                        em = f < em ? f : em;
+                    }
+                    if (pt) {
+                        ndot += (u64)__popc(pt);
+                        const u64 l = (u64)(i + last_byte(pt)) + 1;
+                        dpos = l > dpos ? l : dpos;
+                    }
+                    if (sg) {
+                        nsg += (u64)__popc(sg);
+                        const u64 l = (u64)(i + last_byte(sg)) + 1;
+                        spos = l > spos ? l : spos;
+                    }
+                    nbad += (u64)__popc(nd & ~pt & ~mk & ~sg);
                 });
-            u64 ebad = 0, efnz = NONE;
-            if (E < e)
+            rmin(0, em);
+            rsum(1, ne);
+            rsum(2, ndot);
+            rmax(3, dpos);
+            rsum(4, nbad);
+            rsum(5, nsg);
+            rmax(6, spos);
+            rmin(8, fnz);
+            rmax(9, lnz);
+            __syncthreads();
+            const u64 nmark = sm.red[1], ndots = sm.red[2], nsigns = sm.red[5];
+            const int64_t E = nmark ? (int64_t)sm.red[0] : e;
+            const bool esg = nsigns == 1 && (int64_t)sm.red[6] - 1 == E + 1;  // the exponent's sign
+            const int64_t x0 = E + 1 + (esg ? 1 : 0);                        // its first digit
+            const int64_t dotpos = ndots ? (int64_t)sm.red[3] - 1 : E;        // the point, or E without one
+            const bool valid = nmark <= 1 && sm.red[4] == 0 && ndots <= 1 && dotpos <= E &&
+                               (E - s0 - (int64_t)ndots) >= 1 &&
+                               (nmark ? (nsigns == 0 || esg) && x0 < e : nsigns == 0);
+            const u64 F = sm.red[8] != NONE && (int64_t)sm.red[8] < E ? sm.red[8] : NONE;  // first nonzero mantissa digit
+            const bool exp_nz = valid && nmark && sm.red[9] != 0 && (int64_t)sm.red[9] - 1 > E;
+            if (exp_nz) {
+                // the exponent's first nonzero digit (red[7]), and the
+                // mantissa's last nonzero digit (red[10] + 1) without the
+                // exponent's digits
+                u64 efnz = NONE, mlnz = 0;
                 scan_symbols<NT, SH>(
                     in, x0, e,
                     [&](int64_t i, uint32_t c) {
-                        ebad |= (u64)(c - '0' > 9u);
                         if (c - '1' < 9u && (u64)i < efnz) efnz = (u64)i;
                     },
                     [&](int64_t i, uint32_t w) {
-                        const uint32_t nd = nondigit_bytes(w), nz = ~nd & ~zerodigit_bytes(w) & 0x80808080u;
-                        ebad |= (u64)(nd != 0u);
+                        const uint32_t nz = ~nondigit_bytes(w) & ~zerodigit_bytes(w) & 0x80808080u;
                         if (nz && (u64)(i + first_byte(nz)) < efnz) efnz = (u64)(i + first_byte(nz));
                     });
-            rsum(1, ndot);
-            rmax(2, dpos);
-            rsum(3, nbad);
-            rmin(4, fnz);
-            rmax(5, lnz);
-            rsum(6, ebad);
-            rmin(7, efnz);
-            __syncthreads();
-            const u64 ndots = sm.red[1], F = sm.red[4];
-            const int64_t dotpos = ndots ? (int64_t)sm.red[2] - 1 : E;  // the point, or E without one
-            const int64_t L = (int64_t)sm.red[5] - 1;                  // the last nonzero digit
-            const bool valid = sm.red[3] == 0 && ndots <= 1 && (E - s0 - (int64_t)ndots) >= 1 &&
-                               (E == e || (x0 < e && sm.red[6] == 0));
+                if (F != NONE)
+                    scan_symbols<NT, SH>(
+                        in, (int64_t)F, E,
+                        [&](int64_t i, uint32_t c) {
+                            if (c - '1' < 9u && (u64)i + 1 > mlnz) mlnz = (u64)i + 1;
+                        },
+                        [&](int64_t i, uint32_t w) {
+                            const uint32_t nz = ~nondigit_bytes(w) & ~zerodigit_bytes(w) & 0x80808080u;
+                            if (nz && (u64)(i + last_byte(nz)) + 1 > mlnz) mlnz = (u64)(i + last_byte(nz)) + 1;
+                        });
+                rmin(7, efnz);
+                rmax(10, mlnz);
+                __syncthreads();
+            }
+            const int64_t L = (exp_nz ? (int64_t)sm.red[10] : (int64_t)sm.red[9]) - 1;  // the last nonzero mantissa digit
             // significant digits from the first nonzero one, the point skipped
             auto sigidx = [&](int64_t i) -> int64_t { return (i - (int64_t)F) - (ndots && dotpos > (int64_t)F && dotpos < i ? 1 : 0); };
             if (valid && F != NONE) {
