@@ -63,6 +63,41 @@ def test_infer_types_matches_oracle(seed):
                          D.TIMESTAMP_S, D.STRING]
 
 
+def test_infer_types_long_fields():
+    """Fields of 4,096 bytes or more are checked by a whole workgroup: long
+    integers (leading zeros, the 19-digit limit), long floats (many digits,
+    exponents with leading zeros), long text and each way of breaking a
+    grammar, alone in a column or beside short fields; with enough of them
+    that some exceed the workgroup queue and are checked by their thread."""
+    rnd = random.Random(21)
+    z = lambda k: "0" * k
+    digits = lambda k: "".join(rnd.choice("0123456789") for _ in range(k))
+    cols = [
+        [z(5000) + "42", "7", z(9000) + "9223372036854775807", "-" + z(4100) + "9223372036854775808"],  # INT64
+        [z(5000) + "42", z(4200) + "9223372036854775808"],                              # FLOAT64 (overflow)
+        ["1." + digits(6000), "2.5", digits(5000) + "e-" + z(4000) + "17", "." + digits(4500)],  # FLOAT64
+        [digits(4000) + "x", "5"],                                                     # STRING
+        ["1e" + z(4500), "1" + z(4200) + "e+5"],                                        # FLOAT64
+        [z(4300) + "1.2.3", "1"],                                                      # STRING
+        ["+" + z(4400) + "-1", "2"],                                                   # STRING
+        ["-" + digits(4096), "3"],                                                     # FLOAT64 or INT64
+        [z(4097) + "e", "1.5"],                                                        # STRING
+    ]
+    nrows = 3000
+    rows = []
+    for r in range(nrows):
+        rows.append(",".join(c[r % len(c)] if r % 3 == 0 else c[1 % len(c)] for c in cols))
+    text = ("\n".join(rows) + "\n").encode()
+    arr = u8(text)
+    R, F = oracle.count(arr, D.csv4())
+    d = dev(arr)
+    raw = pp.parse(d, D.csv4(), [D.STRING] * len(cols), R, F)
+    types, nonempty = pp.infer_types(d, raw)
+    want, wn = oracle.infer_types(arr, D.csv4(), len(cols))
+    assert types == want and list(nonempty) == list(wn)
+    assert types[:7] == [D.INT64, D.FLOAT64, D.FLOAT64, D.STRING, D.FLOAT64, D.STRING, D.STRING]
+
+
 def test_parse_inferred_numeric_slice():
     """The numeric CSV without a schema: column count, string parse, types,
     typed parse; the inferred schema is the generator's."""
