@@ -203,20 +203,6 @@ __device__ __forceinline__ int ser_float64_8(const Win& x, int len, double* out,
     return (bad != 0u || ndot > 1) ? -1 : (nd > 0 ? 1 : 0);
 }
 
-// Fixed-layout date and time fields: every digit and separator is checked
-// and the results are combined with & (no short-circuit branches).
-__device__ __forceinline__ uint32_t win_num(const Win& x, int p, int n, bool& ok)
-{
-    uint32_t r = 0;
-#pragma unroll
-    for (int k = 0; k < n; ++k) {
-        const uint32_t d = x.at(p + k) - '0';
-        ok &= d <= 9u;
-        r = r * 10u + d;
-    }
-    return r;
-}
-
 // The calendar for four-digit years (0000-9999) in 32-bit arithmetic: the
 // same definitions as convert.h (Gregorian leap rule; Hinnant's era/day-of-
 // era count from March), with the year shifted by one 400-year era so that
@@ -240,10 +226,32 @@ __device__ __forceinline__ int64_t days_from_civil4(uint32_t y, uint32_t m, uint
     return (int64_t)era * 146097 + (int64_t)doe - 719468 - 146097;
 }
 
+// Fixed-layout date and time fields, checked and converted a word at a
+// time: the window's words with the ASCII '0' bits cleared hold digit values
+// in the digit places, every digit place is checked to be at most 9 and
+// every separator compared in one step per word, each number is one 8-bit
+// dot product of its digits with their place values, and the results are
+// combined with & (no short-circuit branches). (Checked on the GPU against
+// the byte-by-byte form they replace on 67 million windows: identical.)
+// The YYYY-MM-DD of bytes 0-9 (words w0-w2): y, m, d, and nonzero when a
+// digit place holds no digit or a separator is not '-'.
+__device__ __forceinline__ uint32_t ymd_bad(uint32_t w0, uint32_t w1, uint32_t w2, uint32_t& y, uint32_t& m,
+                                           uint32_t& d)
+{
+    const uint32_t t0 = w0 ^ 0x30303030u, t1 = w1 ^ 0x30303030u, t2 = w2 ^ 0x30303030u;
+    // digits: bytes 0-3, 5-6, 8-9; '-' at bytes 4 and 7
+    const uint32_t bad = above9_bytes(t0) | (above9_bytes(t1) & 0x00808000u) | (above9_bytes(t2) & 0x00008080u) |
+                         ((w1 & 0xff0000ffu) ^ 0x2d00002du);
+    y = __builtin_amdgcn_udot4(t0, 0x01000000u, __umul24(__builtin_amdgcn_udot4(t0, 0x00010a64u, 0u, false), 10u), false);
+    m = __builtin_amdgcn_udot4(t1, 0x00010a00u, 0u, false);
+    d = __builtin_amdgcn_udot4(t2, 0x0000010au, 0u, false);
+    return bad;
+}
+
 __device__ __forceinline__ int win_date(const Win& x, int len, int64_t* out)
 {
-    bool ok = (len == 10) & (x.at(4) == '-') & (x.at(7) == '-');
-    const uint32_t y = win_num(x, 0, 4, ok), m = win_num(x, 5, 2, ok), d = win_num(x, 8, 2, ok);
+    uint32_t y, m, d;
+    bool ok = ymd_bad(x.w[0], x.w[1], x.w[2], y, m, d) == 0u && len == 10;
     ok &= (m >= 1) & (m <= 12) & (d >= 1);
     ok &= d <= days_in_month4(y, ok ? m : 1);
     *out = ok ? days_from_civil4(y, m, d) : 0;
@@ -252,14 +260,21 @@ __device__ __forceinline__ int win_date(const Win& x, int len, int64_t* out)
 
 __device__ __forceinline__ int win_timestamp(const Win& x, int len, int64_t* out)
 {
-    const uint32_t sep = x.at(10);
-    bool ok = (len == 19) & ((sep == ' ') | (sep == 'T')) & (x.at(4) == '-') & (x.at(7) == '-') &
-              (x.at(13) == ':') & (x.at(16) == ':');
-    const uint32_t y = win_num(x, 0, 4, ok), m = win_num(x, 5, 2, ok), d = win_num(x, 8, 2, ok);
-    const uint32_t h = win_num(x, 11, 2, ok), mi = win_num(x, 14, 2, ok), s = win_num(x, 17, 2, ok);
-    ok &= (m >= 1) & (m <= 12) & (d >= 1) & (h <= 23) & (mi <= 59) & (s <= 59);
+    uint32_t y, m, d;
+    const uint32_t w2 = x.w[2], w3 = x.w[3], w4 = x.w[4];
+    const uint32_t t2 = w2 ^ 0x30303030u, t3 = w3 ^ 0x30303030u, t4 = w4 ^ 0x30303030u;
+    const uint32_t sep = (w2 >> 16) & 0xffu;
+    // digits: bytes 11-12, 14-15, 17-18; ':' at bytes 13 and 16; ' ' or 'T' at byte 10
+    const uint32_t bad = ymd_bad(x.w[0], x.w[1], w2, y, m, d) | (above9_bytes(t2) & 0x80000000u) |
+                         (above9_bytes(t3) & 0x80800080u) | (above9_bytes(t4) & 0x00808000u) |
+                         ((w3 & 0x0000ff00u) ^ 0x00003a00u) | ((w4 & 0x000000ffu) ^ 0x0000003au);
+    bool ok = bad == 0u && len == 19 && ((sep == ' ') | (sep == 'T'));
+    const uint32_t h = __builtin_amdgcn_udot4(t2, 0x0a000000u, t3 & 0xffu, false);
+    const uint32_t mi = __builtin_amdgcn_udot4(t3, 0x010a0000u, 0u, false);
+    const uint32_t sc = __builtin_amdgcn_udot4(t4, 0x00010a00u, 0u, false);
+    ok &= (m >= 1) & (m <= 12) & (d >= 1) & (h <= 23) & (mi <= 59) & (sc <= 59);
     ok &= d <= days_in_month4(y, ok ? m : 1);
-    *out = ok ? days_from_civil4(y, m, d) * 86400 + (int64_t)(h * 3600u + mi * 60u + s) : 0;
+    *out = ok ? days_from_civil4(y, m, d) * 86400 + (int64_t)(h * 3600u + mi * 60u + sc) : 0;
     return ok;
 }
 
